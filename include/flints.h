@@ -1,0 +1,180 @@
+/*
+ * flints.h -- C ABI of the MI355X FLINTS interpolation library (libflints.so).
+ *
+ * FLINTS (Lavaux & Wandelt, "Fast and optimal CMB lensing using statistical
+ * interpolation on the sphere") predicts the value of an isotropic Gaussian
+ * random field at an arbitrary direction from the values sampled on a stencil
+ * of HEALPix pixels, using the field's angular power spectrum: the Gaussian
+ * conditional mean (kriging), together with its error variance.
+ *
+ * For every target direction the library
+ *   1. finds the K nearest RING pixel centres (chord distance, ties to the
+ *      smaller pixel index) -- the stencil of paper Sec. 2.3, read as "K nearest";
+ *   2. gathers their values from a RING-ordered map;
+ *   3. assembles the K x K neighbour covariance S and the target-neighbour vector
+ *      b from the correlation function tabulated at plan time -- spin 0:
+ *      Sec. 2.1, Eq. correlation_func / fundamental_variance; spin 2: Sec. 2.2,
+ *      Eq. spins_correl / v_spins, with parallel-transport phases;
+ *   4. factorises S + n I (Cholesky, nugget n of Sec. 2.4) and solves;
+ *   5. returns the weighted value (Eq. best_temperature_field, Eq. major_eq)
+ *      and, if asked, the kriging variance (Eq. gaussvar, Eq. gaussvar_pol).
+ *
+ * Conventions
+ *   - All device arrays are plain device pointers (hipMalloc'ed or equivalent);
+ *     the caller owns every array passed in.  A plan owns its device tables.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is enqueued on that stream; calls return once the
+ *     work is enqueued, without synchronising.
+ *   - Return codes: FLINTS_OK (0) or a negative FLINTS_E* code; the message of
+ *     the last failure on the calling thread is available from
+ *     flints_last_error().  Nothing throws across this ABI.
+ *   - Per-point problems never abort a launch: a target with theta outside
+ *     [0, pi] or a non-finite angle yields NaN outputs and is counted in the
+ *     plan's statistics.
+ */
+#ifndef FLINTS_H
+#define FLINTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct flints_plan_s *flints_plan_t;   /* opaque, immutable after creation */
+
+enum {
+  FLINTS_OK = 0,
+  FLINTS_EINVAL = -1,    /* invalid argument (message says which) */
+  FLINTS_ENOMEM = -2,    /* device or host allocation failed */
+  FLINTS_EDEVICE = -3,   /* a HIP runtime call failed */
+  FLINTS_ELIMIT = -4     /* request exceeds a documented size limit */
+};
+
+enum { FLINTS_FP64 = 0, FLINTS_FP32_IR = 1 };
+enum { FLINTS_S2_FULL = 0, FLINTS_S2_PAPER = 1 };
+enum { FLINTS_NUG_ALWAYS = 0, FLINTS_NUG_ON_FAILURE = 1 };
+enum { FLINTS_VAR_PAPER = 0, FLINTS_VAR_MSE = 1 };
+
+typedef struct {
+  /* FLINTS_FP64: every step in double precision.
+   * FLINTS_FP32_IR: covariance entries and residuals in FP64, factorisation and
+   *   solves in FP32 with one step of iterative refinement; neighbourhoods whose
+   *   FP32 factorisation fails the pivot-ratio or refinement-convergence test are
+   *   recomputed in FP64 (counted in flints_stats.fp64_fallbacks). */
+  int precision;
+  /* Spin 2 only.  FLINTS_S2_FULL (default): exact Gaussian conditional mean of
+   * (Q, U) from both <P P*> (xi_+) and <P P> (xi_-), a real 2K x 2K system.
+   * FLINTS_S2_PAPER: the Hermitian complex K x K estimator of Sec. 2.2 (xi_- = 0). */
+  int spin2_mode;
+  /* FLINTS_NUG_ALWAYS (default): S + eps I with eps = 2^-26 (= 1.49e-8, the value
+   * Sec. 2.4 gives for double precision); if that factorisation still fails the
+   * nugget becomes -lambda_min(S) + eps.  FLINTS_NUG_ON_FAILURE: the paper's
+   * literal rule, no nugget unless the factorisation of S fails. */
+  int nugget;
+  /* FLINTS_VAR_PAPER (default): sigma^2 (1 - b^T w), Eq. gaussvar with S + n I.
+   * FLINTS_VAR_MSE: additionally subtracts sigma^2 n |w|^2, the exact mean
+   * squared error of the regularised weights. */
+  int var_kind;
+  /* Maximum absolute error of the tabulated, cubic-interpolated correlation
+   * function relative to its zero-lag value (0 = default 1e-12). */
+  double table_tol;
+  /* FP32_IR thresholds (0 = defaults): minimum ratio min_k L_kk / max_k L_kk of
+   * the FP32 factor, and maximum |dw| / |w| of the refinement step. */
+  double pivot_ratio_min;
+  double refine_tol;
+} flints_opts;
+
+/* Fill *o with the defaults above. */
+void flints_default_opts(flints_opts *o);
+
+/*
+ * Create a plan (paper Sec. 2.5, preparation steps 1-2: resolution, band limit
+ * and the tabulated correlation function).
+ *   nside  HEALPix resolution, 1 <= nside <= 8192.
+ *   lmax   band limit, 1 <= lmax <= 16384 (spin 2: >= 2).
+ *   cl     host array.  spin 0: C^TT_l for l = 0..lmax (l = 0 ignored, Eq.
+ *          correlation_func sums from l = 1).  spin 2: C^EE_l for l = 0..lmax
+ *          followed by C^BB_l for l = 0..lmax (l < 2 ignored).  Must be finite
+ *          and non-negative; read during the call only.
+ *   K      stencil size, 1 <= K <= min(64, 12 nside^2) for spin 0 and
+ *          1 <= K <= 32 for spin 2.
+ *   spin   0 (temperature) or 2 (Q, U polarisation).
+ * The correlation function is built on the current HIP device in FP64 and kept
+ * in device memory.  Returns NULL on error (see flints_last_error()).
+ */
+flints_plan_t flints_plan(int64_t nside, int lmax, const double *cl, int K, int spin);
+flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, int spin,
+                             const flints_opts *opts);
+
+/*
+ * Interpolate a RING map at n target directions (paper Sec. 2.5, steps 4-6).
+ *   map    device, RING order.  spin 0: double[npix].  spin 2: double[2*npix],
+ *          the Q plane followed by the U plane.
+ *   theta  device double[n], colatitude in [0, pi].
+ *   phi    device double[n], longitude, any real (reduced modulo 2 pi).
+ *   out    device.  spin 0: double[n].  spin 2: double[2*n] = (Q[n], U[n]).
+ *   var    device, nullable (variance is then not written).  Same layout as out.
+ * Q and U are Stokes parameters in the local (e_theta, e_phi) frame with
+ * P = Q + iU = sum 2a_lm 2Y_lm, 2a_lm = -(E_lm + i B_lm), and
+ * sY_lm = (-1)^s sqrt((2l+1)/4pi) e^{i m phi} d^l_{m,-s}(theta) (paper App. A).
+ * n = 0 is a no-op.  Concurrent calls with one plan on different streams are
+ * allowed.
+ */
+int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
+                       const double *phi, int64_t n, void *out, void *var, void *stream);
+
+/*
+ * Stencil of each target: the K nearest RING pixels, ascending distance, ties to
+ * the smaller index (paper Sec. 2.3 step, read as K nearest).
+ *   idx    device int64[n*K], row-major; rows of invalid targets are -1.
+ */
+int flints_stencil(flints_plan_t plan, const double *theta, const double *phi, int64_t n,
+                   int64_t *idx, void *stream);
+
+/*
+ * Evaluate the plan's tabulated correlation function (paper App. B: tabulated
+ * and interpolated with cubics) at n chord half-lengths s = sin(beta/2).
+ *   s      device double[n], 0 <= s <= plan's table range.
+ *   out    device double[n*nf], nf = 1 (spin 0: zeta/zeta(0)) or 2 (spin 2:
+ *          xi_+/xi_+(0), xi_-/xi_+(0)), row-major.
+ */
+int flints_table_eval(flints_plan_t plan, const double *s, int64_t n, double *out, void *stream);
+
+typedef struct {
+  int64_t nside;
+  int lmax, K, spin;
+  int ntab;              /* table nodes per function */
+  double table_step;     /* node spacing in s = sin(beta/2) */
+  double table_smax;     /* largest s covered */
+  double table_err;      /* measured max interpolation error (relative) */
+  double sigma2;         /* prior variance per output field */
+  double search_r0, search_rcap;   /* stencil search radii (rad) */
+  double nugget_eps;
+} flints_plan_info_t;
+
+int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info);
+
+typedef struct {
+  int64_t bad_inputs;          /* targets with invalid angles */
+  int64_t nugget_escalations;  /* factorisations that needed -lambda_min + eps */
+  int64_t clamped_vars;        /* negative variances clamped to 0 */
+  int64_t fp64_fallbacks;      /* FP32_IR points recomputed in FP64 */
+  int64_t search_failures;     /* targets whose stencil was not found (NaN output) */
+  int64_t table_range;         /* pair distances beyond the table (clamped) */
+} flints_stats;
+
+/* Counters accumulated since plan creation (synchronises the device). */
+int flints_plan_stats(flints_plan_t plan, flints_stats *st);
+int flints_plan_reset_stats(flints_plan_t plan);
+
+/* Release a plan.  The caller must ensure no work using it is in flight. */
+void flints_plan_destroy(flints_plan_t plan);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *flints_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLINTS_H */

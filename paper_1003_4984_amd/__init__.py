@@ -1,0 +1,10 @@
+"""MI355X-native FLINTS: kriging interpolation of spin-0 and spin-2 HEALPix maps.
+
+The compute path is the HIP library libflints.so (C ABI in include/flints.h);
+this package only marshals arguments to it.  Importing the package does not load
+the library; the first call does, and raises if it has not been built.
+"""
+from .flints import (  # noqa: F401
+    Plan, FlintsError, load_library, interpolate, stencil, table_eval,
+    FP64, FP32_IR, S2_FULL, S2_PAPER, NUG_ALWAYS, NUG_ON_FAILURE, VAR_PAPER, VAR_MSE,
+)

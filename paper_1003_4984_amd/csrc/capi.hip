@@ -1,0 +1,233 @@
+// C ABI of libflints: validation, plan lifecycle, statistics and error text.
+// Every entry point catches its own failures and reports them through a return
+// code plus a thread-local message; nothing throws across the boundary.
+#include "plan.h"
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace flints {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+static bool finite_nonneg(const double *v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i]) || v[i] < 0.0) return false;
+  return true;
+}
+
+}  // namespace flints
+
+using namespace flints;
+
+extern "C" {
+
+void flints_default_opts(flints_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = FLINTS_FP64;
+  o->spin2_mode = FLINTS_S2_FULL;
+  o->nugget = FLINTS_NUG_ALWAYS;
+  o->var_kind = FLINTS_VAR_PAPER;
+  o->table_tol = 1e-12;
+  o->pivot_ratio_min = 0.0;
+  o->refine_tol = 0.0;
+}
+
+const char *flints_last_error(void) { return g_last_error.c_str(); }
+
+flints_plan_t flints_plan(int64_t nside, int lmax, const double *cl, int K, int spin) {
+  return flints_plan_ex(nside, lmax, cl, K, spin, nullptr);
+}
+
+flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, int spin,
+                             const flints_opts *opts) {
+  g_last_error.clear();
+  flints_opts o;
+  flints_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.table_tol <= 0.0) o.table_tol = 1e-12;
+  if (nside < 1 || nside > 8192) { set_error("nside must be in [1, 8192]"); return nullptr; }
+  if (spin != 0 && spin != 2) { set_error("spin must be 0 or 2"); return nullptr; }
+  if (lmax < (spin == 0 ? 1 : 2) || lmax > 16384) {
+    set_error("lmax must be in [1, 16384] (spin 2: >= 2)");
+    return nullptr;
+  }
+  if (!cl) { set_error("cl is NULL"); return nullptr; }
+  const int64_t npix = 12 * nside * nside;
+  const int kmax = spin == 0 ? 64 : 32;
+  if (K < 1 || K > kmax || K > npix) {
+    set_error(spin == 0 ? "K must be in [1, min(64, npix)]" : "K must be in [1, min(32, npix)] for spin 2");
+    return nullptr;
+  }
+  if (o.precision != FLINTS_FP64 && o.precision != FLINTS_FP32_IR) { set_error("bad precision"); return nullptr; }
+  if (o.spin2_mode != FLINTS_S2_FULL && o.spin2_mode != FLINTS_S2_PAPER) { set_error("bad spin2_mode"); return nullptr; }
+  if (o.nugget != FLINTS_NUG_ALWAYS && o.nugget != FLINTS_NUG_ON_FAILURE) { set_error("bad nugget policy"); return nullptr; }
+  if (o.var_kind != FLINTS_VAR_PAPER && o.var_kind != FLINTS_VAR_MSE) { set_error("bad var_kind"); return nullptr; }
+  const int ncl = (spin == 0 ? 1 : 2) * (lmax + 1);
+  if (!finite_nonneg(cl, ncl)) { set_error("cl must be finite and non-negative"); return nullptr; }
+
+  // weights (2l+1)/(4 pi) C_l; spin 0 sums from l = 1, spin 2 from l = 2
+  std::vector<double> wp(lmax + 1, 0.0), wm(lmax + 1, 0.0);
+  const double inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
+  for (int l = 0; l <= lmax; ++l) {
+    const double f = (2.0 * l + 1.0) * inv4pi;
+    if (spin == 0) {
+      if (l >= 1) wp[l] = f * cl[l];
+    } else if (l >= 2) {
+      const double ee = cl[l], bb = cl[lmax + 1 + l];
+      wp[l] = f * (ee + bb);
+      wm[l] = f * (ee - bb);
+    }
+  }
+  double s0 = 0.0;
+  for (int l = 0; l <= lmax; ++l) s0 += wp[l];
+  if (!(s0 > 0.0)) { set_error("the spectrum has no power in the summed range"); return nullptr; }
+
+  Plan *p = new (std::nothrow) Plan();
+  if (!p) { set_error("host allocation failed"); return nullptr; }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    delete p;
+    set_error("no HIP device available");
+    return nullptr;
+  }
+  p->device = dev;
+  p->lmax = lmax;
+  PlanDev &d = p->d;
+  d.nside = nside;
+  d.npix = npix;
+  d.K = K;
+  d.spin = spin;
+  d.mode = o.spin2_mode;
+  d.nug_policy = o.nugget;
+  d.var_kind = o.var_kind;
+  d.precision = o.precision;
+  d.n = spin == 0 ? K : 2 * K;
+  d.eps = 1.4901161193847656e-08;  // 2^-26 = sqrt(double epsilon), paper Sec. 2.4
+  d.sigma2 = spin == 0 ? s0 : 0.5 * s0;
+  d.pivot_ratio_min = o.pivot_ratio_min > 0.0 ? o.pivot_ratio_min : 1e-3;
+  d.refine_tol = o.refine_tol > 0.0 ? o.refine_tol : 1e-3;
+  // Search radii from the expected pixel count in a cap: N(r) = 6 nside^2 (1 - cos r).
+  // r0 holds ~2K pixels on average, rcap ~5K; the table covers pair separations up
+  // to 2 rcap, i.e. s = sin(beta/2) <= sin(rcap).
+  const double n2 = (double)nside * (double)nside;
+  auto cap_radius = [&](double count) {
+    double c = 1.0 - count / (6.0 * n2);
+    if (c <= -1.0) return 3.14159265358979323846;
+    return std::acos(c);
+  };
+  d.r0 = cap_radius(2.0 * K);
+  d.rcap = std::max(d.r0, cap_radius(5.0 * K + 8.0));
+  d.smax = d.rcap >= 0.5 * 3.14159265358979323846 ? 1.0 : std::min(1.0, std::sin(d.rcap) * 1.0001);
+
+  int rc = build_table(p, wp.data(), spin == 2 ? wm.data() : nullptr, o.table_tol);
+  if (rc != FLINTS_OK) {
+    delete p;
+    return nullptr;
+  }
+  if (hipMalloc(&p->d_counters, sizeof(unsigned long long) * CNT_N) != hipSuccess ||
+      hipMemset(p->d_counters, 0, sizeof(unsigned long long) * CNT_N) != hipSuccess) {
+    hipFree(p->d_tab);
+    delete p;
+    set_error("device allocation of plan counters failed");
+    return nullptr;
+  }
+  d.counters = p->d_counters;
+  return reinterpret_cast<flints_plan_t>(p);
+}
+
+static Plan *as_plan(flints_plan_t h) { return reinterpret_cast<Plan *>(h); }
+
+int flints_interpolate(flints_plan_t plan, const void *map, const double *theta, const double *phi,
+                       int64_t n, void *out, void *var, void *stream) {
+  g_last_error.clear();
+  if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
+  if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
+  if (n == 0) return FLINTS_OK;
+  if (!map || !theta || !phi || !out) { set_error("map, theta, phi and out must be non-NULL"); return FLINTS_EINVAL; }
+  Plan *p = as_plan(plan);
+  return launch_interpolate(p, (const double *)map, theta, phi, n, (double *)out, (double *)var,
+                            (hipStream_t)stream);
+}
+
+int flints_stencil(flints_plan_t plan, const double *theta, const double *phi, int64_t n,
+                   int64_t *idx, void *stream) {
+  g_last_error.clear();
+  if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
+  if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
+  if (n == 0) return FLINTS_OK;
+  if (!theta || !phi || !idx) { set_error("theta, phi and idx must be non-NULL"); return FLINTS_EINVAL; }
+  return launch_stencil(as_plan(plan), theta, phi, n, idx, (hipStream_t)stream);
+}
+
+int flints_table_eval(flints_plan_t plan, const double *s, int64_t n, double *out, void *stream) {
+  g_last_error.clear();
+  if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
+  if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
+  if (n == 0) return FLINTS_OK;
+  if (!s || !out) { set_error("s and out must be non-NULL"); return FLINTS_EINVAL; }
+  return launch_table_eval(as_plan(plan), s, n, out, (hipStream_t)stream);
+}
+
+int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info) {
+  g_last_error.clear();
+  if (!plan || !info) { set_error("plan and info must be non-NULL"); return FLINTS_EINVAL; }
+  const Plan *p = as_plan(plan);
+  info->nside = p->d.nside;
+  info->lmax = p->lmax;
+  info->K = p->d.K;
+  info->spin = p->d.spin;
+  info->ntab = p->d.ntab;
+  info->table_step = p->d.h;
+  info->table_smax = p->d.smax;
+  info->table_err = p->table_err;
+  info->sigma2 = p->d.sigma2;
+  info->search_r0 = p->d.r0;
+  info->search_rcap = p->d.rcap;
+  info->nugget_eps = p->d.eps;
+  return FLINTS_OK;
+}
+
+int flints_plan_stats(flints_plan_t plan, flints_stats *st) {
+  g_last_error.clear();
+  if (!plan || !st) { set_error("plan and stats must be non-NULL"); return FLINTS_EINVAL; }
+  unsigned long long c[CNT_N];
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(c, as_plan(plan)->d_counters, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("reading plan counters failed");
+    return FLINTS_EDEVICE;
+  }
+  st->bad_inputs = (int64_t)c[CNT_BAD_INPUT];
+  st->nugget_escalations = (int64_t)c[CNT_NUGGET_ESC];
+  st->clamped_vars = (int64_t)c[CNT_CLAMPED_VAR];
+  st->fp64_fallbacks = (int64_t)c[CNT_FP64_FALLBACK];
+  st->search_failures = (int64_t)c[CNT_SEARCH_FAIL];
+  st->table_range = (int64_t)c[CNT_TABLE_RANGE];
+  return FLINTS_OK;
+}
+
+int flints_plan_reset_stats(flints_plan_t plan) {
+  g_last_error.clear();
+  if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemset(as_plan(plan)->d_counters, 0, sizeof(unsigned long long) * CNT_N) != hipSuccess) {
+    set_error("resetting plan counters failed");
+    return FLINTS_EDEVICE;
+  }
+  return FLINTS_OK;
+}
+
+void flints_plan_destroy(flints_plan_t plan) {
+  if (!plan) return;
+  Plan *p = as_plan(plan);
+  if (p->d_tab) hipFree(p->d_tab);
+  if (p->d_counters) hipFree(p->d_counters);
+  delete p;
+}
+
+}  // extern "C"

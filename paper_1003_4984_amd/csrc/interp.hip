@@ -1,0 +1,845 @@
+// FLINTS interpolation kernels for gfx950 (CDNA4), double precision.
+//
+// One 64-lane wavefront owns a group of PPW = 64/G target points.  Phase A runs
+// once per point of the group with the whole wave:
+//   a2/a3  K-nearest search: rings crossing a disc of radius r around the target
+//          are listed one per lane, their pixel windows are flattened across the
+//          wave, every lane tests one candidate pixel (chord distance in FP64 from
+//          a difference vector written in the target's rotated frame), survivors
+//          are compacted into LDS, and each candidate's rank (distance, then pixel
+//          index) is counted against all others; ranks < K form the stencil.
+//   a4/a5  per-neighbour record: offset from the target, local e_theta / e_phi,
+//          gathered map values (RING order, so neighbouring targets reuse lines).
+//   a6     every pair (a, b) of {target, neighbours}: half chord s, correlation
+//          from the LDS table (cubic), spin-2 parallel-transport phases from the
+//          bearings, written as the packed lower triangle of S plus the
+//          right-hand sides (target covariances and data) in LDS.
+// Phase B: lane row i of group g holds row i of the augmented system
+// [S + nI | b | data] in registers and runs a right-looking Cholesky with the
+// pivot column broadcast through LDS; carrying the right-hand sides through the
+// elimination gives y = L^-1 b and z = L^-1 data, so
+//   value = y . z = b^T (S+nI)^-1 data   (paper Eq. best_temperature_field / major_eq)
+//   var   = sigma^2 (1 - y . y)          (paper Eq. gaussvar / gaussvar_pol)
+// without a backward solve (one is run only for the MSE variance option).
+// A failed factorisation (non-positive pivot) triggers the nugget escalation of
+// paper Sec. 2.4: bisection for the smallest shift mu with S + mu I positive
+// definite, then n = mu + eps.
+#include "plan.h"
+#include "healpix_ring.h"
+#include "table_interp.h"
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <map>
+
+namespace flints {
+
+constexpr int WAVE = 64;
+constexpr int MAX_WPB = 4;
+constexpr int CAND_CAP = 320;
+constexpr int NBF = 10;  // doubles per neighbour record
+constexpr double PI_D = 3.14159265358979323846;
+constexpr double TWO_PI_D = 6.28318530717958647692;
+
+__device__ inline void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ inline void compiler_fence() { __asm__ volatile("" ::: "memory"); }
+__host__ __device__ inline int tri(int r) { return r * (r + 1) / 2; }
+
+// sin and cos of x for |x| <= 2 pi (all angles here are half longitude
+// differences).  x is reduced by the nearest multiple k of pi/2 with pi/2 split
+// into a double and its remainder (x - k*hi is exact for |k| <= 4), then sin and
+// cos of |r| <= pi/4 come from their Taylor series (truncation < 1e-19).
+__device__ inline void sincos_bounded(double x, double &s, double &c) {
+  const double PIO2_HI = 1.5707963267948966;      // pi/2 rounded to double
+  const double PIO2_LO = 6.123233995736766e-17;   // pi/2 - PIO2_HI
+  const double k = rint(x * 0.6366197723675814);
+  const double r = fma(-k, PIO2_LO, fma(-k, PIO2_HI, x));
+  const double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ... - r^16/17!)
+  double ps = -1.0 / 355687428096000.0;            // -1/17!
+  ps = fma(ps, r2, 1.0 / 1307674368000.0);         // 1/15!
+  ps = fma(ps, r2, -1.0 / 6227020800.0);           // -1/13!
+  ps = fma(ps, r2, 1.0 / 39916800.0);              // 1/11!
+  ps = fma(ps, r2, -1.0 / 362880.0);               // -1/9!
+  ps = fma(ps, r2, 1.0 / 5040.0);                  // 1/7!
+  ps = fma(ps, r2, -1.0 / 120.0);                  // -1/5!... sign pattern continues
+  ps = fma(ps, r2, 1.0 / 6.0);
+  const double sr = fma(-r * r2, ps, r);           // r - r^3 (1/3! - r^2/5! + ...)
+  // cos r = 1 - r^2/2! + r^4/4! - ... + r^16/16!
+  double pc = 1.0 / 20922789888000.0;              // 1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);          // -1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);             // 1/12!
+  pc = fma(pc, r2, -1.0 / 3628800.0);              // -1/10!
+  pc = fma(pc, r2, 1.0 / 40320.0);                 // 1/8!
+  pc = fma(pc, r2, -1.0 / 720.0);                  // -1/6!
+  pc = fma(pc, r2, 1.0 / 24.0);                    // 1/4!
+  pc = fma(pc, r2, -0.5);
+  const double cr = fma(r2, pc, 1.0);
+  const int q = ((int)k) & 3;
+  s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+  c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
+}
+
+// Broadcast a double held by lane `src` (wave-uniform index) to all lanes.
+__device__ inline double readlane_d(double v, int src) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Value of `v` in row k of this lane's group (groups of G lanes).
+template <int G>
+__device__ inline double group_bcast(double v, int k, int grp) {
+  double r = readlane_d(v, k);
+#pragma unroll
+  for (int g = 1; g < WAVE / G; ++g) {
+    const double t = readlane_d(v, g * G + k);
+    r = (grp == g) ? t : r;
+  }
+  return r;
+}
+
+struct RingSpan {
+  double z, s, phi0, dphi;
+  long long first;
+  int n, j0, off, pad;
+};
+
+struct Layout {
+  int tab_bytes, wave_bytes;
+  int off_cu, off_ci, off_rings, off_sel, off_nb, off_mat, off_rhs, off_col, off_rbuf;
+  int matsz;
+};
+
+static inline int al16(int x) { return (x + 15) & ~15; }
+
+static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int G, int NR) {
+  Layout L;
+  L.tab_bytes = al16(ntab * nf * 8);
+  int o = 0;
+  L.off_cu = o;    o = al16(o + (CAND_CAP + 4) * 8);
+  L.off_ci = o;    o = al16(o + (CAND_CAP + 4) * 4);
+  L.off_rings = o; o = al16(o + WAVE * (int)sizeof(RingSpan));
+  L.off_sel = o;   o = al16(o + ppw * K * 4);
+  L.off_nb = o;    o = al16(o + ppw * (K + 1) * NBF * 8);
+  L.matsz = n * (n + 1) / 2;
+  L.off_mat = o;   o = al16(o + ppw * L.matsz * 8);
+  L.off_rhs = o;   o = al16(o + ppw * n * NR * 8);
+  L.off_col = o;
+  L.off_rbuf = o;  o = al16(o + ppw * 4 * 8);
+  L.wave_bytes = o;
+  return L;
+}
+
+__device__ inline void count_event(unsigned long long *ctr, bool cond, int lane) {
+  unsigned long long m = __ballot(cond);
+  if (m && lane == 0) atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
+// ---------------------------------------------------------------- a2/a3 search
+// Candidates within angle r of the target, compacted into (cu, ci).  Returns the
+// number found (entries beyond CAND_CAP are counted but not stored).
+__device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st, double phr,
+                              double r, int lane, double *cu, int *ci, RingSpan *rs) {
+  const int64_t N = P.nside;
+  const double sr = sin(0.5 * r);
+  const double ur = 2.0 * sr * sr;  // 1 - cos r
+  const double cr = cos(r);
+  const bool pn = (th - r) <= 0.0, ps = (th + r) >= PI_D;
+  const double zhi = pn ? 1.0 : cos(th - r);
+  const double zlo = ps ? -1.0 : cos(th + r);
+  int i0 = (int)floor(ring_coord(N, zhi)) - 1;
+  if (i0 < 1) i0 = 1;
+  int i1 = (int)ceil(ring_coord(N, zlo)) + 1;
+  if (i1 > (int)(4 * N - 1)) i1 = (int)(4 * N - 1);
+  int count = 0;
+  for (int ib = i0; ib <= i1; ib += WAVE) {
+    const int i = ib + lane;
+    int m = 0, j0 = 0;
+    if (i <= i1) {
+      const Ring R = ring_geom(N, i);
+      m = R.n;
+      if (!(pn || ps)) {
+        const double c = (cr - zt * R.z) / (st * R.s);
+        if (c > 1.0 + 1e-6) {
+          m = 0;
+        } else if (c > -1.0) {
+          const double half = acos(fmin(c, 1.0)) + R.dphi;
+          if (half < PI_D) {
+            const double inv = (double)R.n * (0.5 / PI_D);
+            const int jlo = (int)floor((phr - half - R.phi0) * inv);
+            const int jhi = (int)ceil((phr + half - R.phi0) * inv);
+            const int span = jhi - jlo + 1;
+            if (span < R.n) {
+              j0 = jlo;
+              m = span;
+            }
+          }
+        }
+      }
+      RingSpan S;
+      S.z = R.z; S.s = R.s; S.phi0 = R.phi0; S.dphi = R.dphi;
+      S.first = R.first; S.n = R.n;
+      int jm = j0 % R.n;
+      if (jm < 0) jm += R.n;
+      S.j0 = jm;
+      S.off = 0;
+      S.pad = 0;
+      rs[lane] = S;
+    }
+    int incl = m;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    const int total = __shfl(incl, WAVE - 1);
+    const int nrg = min(WAVE, i1 - ib + 1);
+    if (i <= i1) rs[lane].off = incl - m;
+    for (int c0 = 0; c0 < total; c0 += WAVE) {
+      const int c = c0 + lane;
+      bool keep = false;
+      double u = 0.0;
+      int pix = 0;
+      if (c < total) {
+        int lo = 0, hi = nrg - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rs[mid].off <= c) lo = mid; else hi = mid - 1;
+        }
+        const RingSpan S = rs[lo];
+        int j = S.j0 + (c - S.off);
+        if (j >= S.n) j -= S.n;
+        const double dphi = S.phi0 + (double)j * S.dphi - phr;
+        double sh, ch;
+        sincos_bounded(0.5 * dphi, sh, ch);
+        const double sdiff = (zt - S.z) * (zt + S.z) / (S.s + st);   // s_ring - s_target
+        const double dx = sdiff - 2.0 * S.s * sh * sh;
+        const double dy = 2.0 * S.s * sh * ch;
+        const double dz = S.z - zt;
+        u = 0.5 * (dx * dx + dy * dy + dz * dz);
+        keep = (u <= ur);
+        pix = (int)(S.first + j);
+      }
+      const unsigned long long mk = __ballot(keep);
+      const int pos = count + __popcll(mk & ((1ull << lane) - 1ull));
+      if (keep && pos < CAND_CAP) {
+        cu[pos] = u;
+        ci[pos] = pix;
+      }
+      count += __popcll(mk);
+    }
+  }
+  return count;
+}
+
+// K nearest pixels of (th, ph), ascending (distance, index), into sel[0..K).
+__device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, double *cu, int *ci,
+                           RingSpan *rs, int *sel) {
+  const double zt = cos(th), st = sin(th);
+  const double phr = ph - TWO_PI_D * floor(ph / TWO_PI_D);
+  const int K = P.K;
+  double r = P.r0, rlo = 0.0, rhi = 0.0;
+  int count = 0;
+  bool ok = false;
+  for (int att = 0; att < 24; ++att) {
+    count = enumerate_disc(P, th, zt, st, phr, r, lane, cu, ci, rs);
+    if (count >= K && count <= CAND_CAP) { ok = true; break; }
+    if (count < K) {
+      if (r >= P.rcap) break;
+      rlo = r;
+      r = (rhi > 0.0) ? 0.5 * (r + rhi) : fmin(1.5 * r, P.rcap);
+    } else {
+      rhi = r;
+      r = 0.5 * (rlo + r);
+    }
+  }
+  if (!ok) return false;
+  // pad to a multiple of 4 with keys that rank after every real candidate
+  const int cpad = (count + 3) & ~3;
+  if (lane < cpad - count) {
+    cu[count + lane] = __builtin_inf();
+    ci[count + lane] = 0x7fffffff;
+  }
+  for (int c = lane; c < count; c += WAVE) {
+    const double uc = cu[c];
+    const int ic = ci[c];
+    int rank = 0;
+    for (int c2 = 0; c2 < cpad; c2 += 4) {
+      const double2 ua = *(const double2 *)(cu + c2);
+      const double2 ub = *(const double2 *)(cu + c2 + 2);
+      const int4 iv = *(const int4 *)(ci + c2);
+      rank += (ua.x < uc) || (ua.x == uc && iv.x < ic);
+      rank += (ua.y < uc) || (ua.y == uc && iv.y < ic);
+      rank += (ub.x < uc) || (ub.x == uc && iv.z < ic);
+      rank += (ub.y < uc) || (ub.y == uc && iv.w < ic);
+    }
+    if (rank < K) sel[rank] = ic;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------- a4/a5 records
+template <int SPIN>
+__device__ void neighbour_records(const PlanDev &P, double th, double ph, int lane, const int *sel,
+                                  double *nb, const double *__restrict__ map) {
+  const double zt = cos(th), st = sin(th);
+  const double phr = ph - TWO_PI_D * floor(ph / TWO_PI_D);
+  const int K = P.K;
+  for (int a = lane; a <= K; a += WAVE) {
+    double *rec = nb + a * NBF;
+    if (a == 0) {
+      rec[0] = 0.0; rec[1] = 0.0; rec[2] = 0.0;
+      rec[3] = zt;  rec[4] = 0.0; rec[5] = -st;
+      rec[6] = 0.0; rec[7] = 1.0;
+      rec[8] = 0.0; rec[9] = 0.0;
+    } else {
+      const int64_t p = sel[a - 1];
+      const Ring R = ring_geom(P.nside, pix_ring(P.nside, p));
+      const double dphi = R.phi0 + (double)(p - R.first) * R.dphi - phr;
+      double sh, ch;
+      sincos_bounded(0.5 * dphi, sh, ch);
+      const double sd = 2.0 * sh * ch, cd = 1.0 - 2.0 * sh * sh;
+      const double sdiff = (zt - R.z) * (zt + R.z) / (R.s + st);
+      rec[0] = sdiff - 2.0 * R.s * sh * sh;
+      rec[1] = R.s * sd;
+      rec[2] = R.z - zt;
+      rec[3] = R.z * cd; rec[4] = R.z * sd; rec[5] = -R.s;
+      rec[6] = -sd;      rec[7] = cd;
+      rec[8] = map[p];
+      rec[9] = (SPIN == 2) ? map[P.npix + p] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- a6 assembly
+template <int SPIN, int NR>
+__device__ void assemble(const PlanDev &P, const double *tab, const double *nb, int lane,
+                         double *mat, double *rhs) {
+  const int K = P.K;
+  const int npairs = (K + 1) * (K + 2) / 2;
+  const bool paper = (P.mode == FLINTS_S2_PAPER);
+  bool range_bad = false;
+  // pair q = a (a + 1) / 2 + b, 0 <= b <= a <= K; lanes stride by WAVE through q
+  int a = 0, b = lane;
+  while (b > a) { b -= a + 1; ++a; }
+  for (int q = lane; q < npairs; q += WAVE) {
+    if (q > 0) {
+      const double *A = nb + a * NBF;
+      const double *B = nb + b * NBF;
+      if (SPIN == 0) {
+        const int ra = a - 1;
+        if (a == b) {
+          mat[tri(ra) + ra] = 1.0;
+          rhs[ra * NR + 1] = A[8];
+        } else {
+          const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+          const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+          double f;
+          range_bad |= !table_lookup(tab, P.ntab, 1, P.inv_h, s, &f);
+          if (b == 0) rhs[ra * NR + 0] = f;
+          else mat[tri(ra) + (b - 1)] = f;
+        }
+      } else {
+        const int ra = 2 * (a - 1);
+        if (a == b) {
+          mat[tri(ra) + ra] = 1.0;
+          mat[tri(ra + 1) + ra] = 0.0;
+          mat[tri(ra + 1) + ra + 1] = 1.0;
+          rhs[ra * NR + 2] = A[8];
+          rhs[(ra + 1) * NR + 2] = A[9];
+        } else {
+          const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+          const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+          double f[2];
+          range_bad |= !table_lookup(tab, P.ntab, 2, P.inv_h, s, f);
+          // bearings: e^{2 i psi} from the chord projected on each point's (e_theta, e_phi)
+          const double xa = dx * A[3] + dy * A[4] + dz * A[5];
+          const double ya = dx * A[6] + dy * A[7];
+          const double xb = dx * B[3] + dy * B[4] + dz * B[5];
+          const double yb = dx * B[6] + dy * B[7];
+          const double na = xa * xa + ya * ya, nbn = xb * xb + yb * yb;
+          const double prod = na * nbn;
+          double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
+          if (prod > 0.0) {
+            const double inv = 1.0 / prod;
+            const double ia = nbn * inv, ib = na * inv;
+            ca = (xa * xa - ya * ya) * ia; sa = 2.0 * xa * ya * ia;
+            cb = (xb * xb - yb * yb) * ib; sb = 2.0 * xb * yb * ib;
+          } else {
+            if (na > 0.0) { const double in = 1.0 / na; ca = (xa * xa - ya * ya) * in; sa = 2.0 * xa * ya * in; }
+            if (nbn > 0.0) { const double in = 1.0 / nbn; cb = (xb * xb - yb * yb) * in; sb = 2.0 * xb * yb * in; }
+          }
+          // <P_a P_b*> = xi+ e^{2i(psi_ab - psi_ba)},  <P_a P_b> = xi- e^{2i(psi_ab + psi_ba)}
+          const double gr = f[0] * (ca * cb + sa * sb), gi = f[0] * (sa * cb - ca * sb);
+          const double pr = paper ? 0.0 : f[1] * (ca * cb - sa * sb);
+          const double pim = paper ? 0.0 : f[1] * (sa * cb + ca * sb);
+          const double QQ = gr + pr, UU = gr - pr, QU = pim - gi, UQ = pim + gi;
+          if (b == 0) {
+            rhs[ra * NR + 0] = QQ;        // Cov(Q_a, Q_0)
+            rhs[(ra + 1) * NR + 0] = UQ;  // Cov(U_a, Q_0)
+            rhs[ra * NR + 1] = QU;        // Cov(Q_a, U_0)
+            rhs[(ra + 1) * NR + 1] = UU;  // Cov(U_a, U_0)
+          } else {
+            const int rb = 2 * (b - 1);
+            mat[tri(ra) + rb] = QQ;
+            mat[tri(ra) + rb + 1] = QU;
+            mat[tri(ra + 1) + rb] = UQ;
+            mat[tri(ra + 1) + rb + 1] = UU;
+          }
+        }
+      }
+    }
+    b += WAVE;
+    while (b > a) { b -= a + 1; ++a; }
+  }
+  count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
+}
+
+// ---------------------------------------------------------------- phase B
+// Full symmetric row `row` of the group's system into registers (the upper part
+// is read from the mirrored packed entry); rows past n and rows of inactive
+// groups become identity rows with zero right-hand sides, which leave the
+// factorisation of the real rows untouched.
+template <int NMAX, int NR>
+__device__ inline void load_rows(const double *mat, const double *rhs, int row, bool act, int nrow,
+                                 double (&a)[NMAX], double (&r)[NR]) {
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    const int idx = (j <= row) ? tri(row) + j : tri(j) + row;
+    // columns past n stay exactly zero in real rows (padding must not see garbage)
+    a[j] = act ? ((j < nrow) ? mat[idx] : 0.0) : (j == row ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < NR; ++q) r[q] = act ? rhs[row * NR + q] : 0.0;
+}
+
+// Right-looking Cholesky of the group's rows (all NMAX steps) with the
+// right-hand sides carried along.  Every lane updates its whole row, so the
+// matrix stays symmetric and the column needed at step k equals row k, held by
+// one lane: pivot, column and the pivot row's right-hand sides are broadcast
+// with readlane (no LDS traffic).  Steps are generated by template recursion so
+// every register index is a compile-time constant.
+template <int NMAX, int G, int NR, int K>
+__device__ __forceinline__ void chol_step(double (&a)[NMAX], double (&r)[NR], int row, int grp,
+                                          double nug, bool &ok, double &mydiag) {
+  const double d = group_bcast<G>(a[K], K, grp) + nug;
+  ok = ok && (d > 0.0);
+  const double rs = rsqrt(d);
+  const double c = a[K] * rs * rs;
+#pragma unroll
+  for (int j = K + 1; j < NMAX; ++j) a[j] = fma(-c, group_bcast<G>(a[j], K, grp), a[j]);
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const double yk = group_bcast<G>(r[q], K, grp);
+    r[q] = (row > K) ? fma(-c, yk, r[q]) : r[q];
+  }
+  const double piv = d * rs;
+  if (row == K) mydiag = piv;
+  a[K] = (row == K) ? piv : a[K] * rs;
+  if constexpr (K + 1 < NMAX) chol_step<NMAX, G, NR, K + 1>(a, r, row, grp, nug, ok, mydiag);
+}
+
+template <int NMAX, int G, int NR>
+__device__ __forceinline__ bool chol_rows(double (&a)[NMAX], double (&r)[NR], int row, int grp,
+                                          double nug, double &mydiag) {
+  bool ok = true;
+  mydiag = 1.0;
+  chol_step<NMAX, G, NR, 0>(a, r, row, grp, nug, ok, mydiag);
+  return ok;
+}
+
+template <int G>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+// ---------------------------------------------------------------- kernel
+// Output value that marks a point whose factorisation failed in the main pass
+// (a quiet NaN with a private payload); the escalation pass recomputes exactly
+// these points.
+constexpr unsigned long long FAIL_BITS = 0x7ff80000000f1a7ull;
+
+// Phase A for one point with the whole wave; returns false if the point is
+// invalid or its stencil was not found.
+template <int SPIN, int NR>
+__device__ inline bool phase_a(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                               double th, double ph, int lane, double *cu, int *ci, RingSpan *rs,
+                               int *sel, double *nb, double *mat, double *rhs) {
+  const bool good = (th >= 0.0) && (th <= PI_D) && isfinite(ph);
+  if (!good) {
+    if (lane == 0) atomicAdd(P.counters + CNT_BAD_INPUT, 1ull);
+    return false;
+  }
+  if (!knn_search(P, th, ph, lane, cu, ci, rs, sel)) {
+    if (lane == 0) atomicAdd(P.counters + CNT_SEARCH_FAIL, 1ull);
+    return false;
+  }
+  neighbour_records<SPIN>(P, th, ph, lane, sel, nb, map);
+  assemble<SPIN, NR>(P, tab, nb, lane, mat, rhs);
+  return true;
+}
+
+struct WaveBufs {
+  double *cu; int *ci; RingSpan *rs; int *sel; double *nb; double *mat; double *rhs; double *rbuf;
+};
+
+__device__ inline WaveBufs wave_bufs(char *lds, const Layout &L, int wave) {
+  char *wb = lds + L.tab_bytes + wave * L.wave_bytes;
+  WaveBufs B;
+  B.cu = (double *)(wb + L.off_cu);
+  B.ci = (int *)(wb + L.off_ci);
+  B.rs = (RingSpan *)(wb + L.off_rings);
+  B.sel = (int *)(wb + L.off_sel);
+  B.nb = (double *)(wb + L.off_nb);
+  B.mat = (double *)(wb + L.off_mat);
+  B.rhs = (double *)(wb + L.off_rhs);
+  B.rbuf = (double *)(wb + L.off_rbuf);
+  return B;
+}
+
+__device__ inline const double *load_table(char *lds, const PlanDev &P) {
+  const int ntabd = P.ntab * P.nfun;
+  for (int i = threadIdx.x; i < ntabd; i += blockDim.x) ((double *)lds)[i] = P.tab[i];
+  __syncthreads();
+  return (const double *)lds;
+}
+
+// Writes the outputs of point pt from the group reductions (lane row == 0).
+template <int SPIN>
+__device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool gact, bool ok,
+                                   double v0, double v1, double qd0, double qd1, double w0,
+                                   double w1, double nug, bool mse, double *out, double *var) {
+  const double nan = __builtin_nan("");
+  const double fail = __longlong_as_double((long long)FAIL_BITS);
+  const double s2 = P.sigma2;
+  const bool good = gact && ok;
+  const double bad = (gact && !ok) ? fail : nan;
+  if (SPIN == 0) {
+    double vv = s2 * (1.0 - qd0);
+    if (mse) vv -= s2 * nug * w0;
+    if (good && vv < 0.0) { atomicAdd(P.counters + CNT_CLAMPED_VAR, 1ull); vv = 0.0; }
+    out[pt] = good ? v0 : bad;
+    if (var) var[pt] = good ? vv : nan;
+  } else {
+    double vq = s2 * (1.0 - qd0), vu = s2 * (1.0 - qd1);
+    if (mse) { vq -= s2 * nug * w0; vu -= s2 * nug * w1; }
+    if (good && (vq < 0.0 || vu < 0.0)) {
+      atomicAdd(P.counters + CNT_CLAMPED_VAR, 1ull);
+      vq = fmax(vq, 0.0);
+      vu = fmax(vu, 0.0);
+    }
+    out[pt] = good ? v0 : bad;
+    out[n + pt] = good ? v1 : bad;
+    if (var) {
+      var[pt] = good ? vq : nan;
+      var[n + pt] = good ? vu : nan;
+    }
+  }
+}
+
+// Group epilogue: y = L^-1 b, z = L^-1 data from the carried right-hand sides,
+// value = y.z and quad = y.y per point by group reductions; with MSE also
+// |w|^2 = |L^-T y|^2 by a backward substitution through LDS.
+template <int NMAX, int G, int SPIN, int NR, bool MSE>
+__device__ inline void epilogue(const PlanDev &P, const double (&a)[NMAX], const double (&r)[NR],
+                                double diag, bool gact, bool ract, int row, double *mat,
+                                double *rbuf, double &v0, double &v1, double &qd0, double &qd1,
+                                double &w0, double &w1) {
+  const double inv = 1.0 / diag;
+  const double y0 = ract ? r[0] * inv : 0.0;
+  const double y1 = ract ? r[1] * inv : 0.0;
+  const double y2 = (ract && NR > 2) ? r[NR - 1] * inv : 0.0;
+  v1 = 0.0;
+  qd1 = 0.0;
+  if (SPIN == 0) {
+    v0 = group_sum<G>(y0 * y1);
+    qd0 = group_sum<G>(y0 * y0);
+  } else {
+    v0 = group_sum<G>(y0 * y2);
+    v1 = group_sum<G>(y1 * y2);
+    qd0 = group_sum<G>(y0 * y0);
+    qd1 = group_sum<G>(y1 * y1);
+  }
+  w0 = 0.0;
+  w1 = 0.0;
+  if (MSE) {
+    const int nrow = P.n;
+    if (ract) {
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j)
+        if (j < row) mat[tri(row) + j] = a[j];
+    }
+    wave_lds_sync();
+    double x0 = y0, x1 = y1;
+#pragma unroll 1
+    for (int k = nrow - 1; k >= 0; --k) {
+      if (row == k && gact) {
+        x0 *= inv;
+        x1 *= inv;
+        rbuf[0] = x0;
+        rbuf[1] = x1;
+      }
+      wave_lds_sync();
+      const double b0 = rbuf[0], b1 = rbuf[1];
+      if (gact && row < k) {
+        const double l = mat[tri(k) + row];
+        x0 = fma(-l, b0, x0);
+        x1 = fma(-l, b1, x1);
+      }
+      wave_lds_sync();
+    }
+    w0 = group_sum<G>(ract ? x0 * x0 : 0.0);
+    w1 = group_sum<G>(ract ? x1 * x1 : 0.0);
+  }
+}
+
+// Main pass over all targets.  MSE adds the MSE variance; a factorisation that
+// fails (non-positive pivot) leaves a tagged NaN for the escalation pass.
+template <int NMAX, int G, int SPIN, bool MSE>
+__global__ __launch_bounds__(256) void k_interp64(PlanDev P, const double *__restrict__ map,
+                                                  const double *__restrict__ theta,
+                                                  const double *__restrict__ phi, int64_t n,
+                                                  double *__restrict__ out,
+                                                  double *__restrict__ var, Layout L) {
+  constexpr int PPW = WAVE / G;
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  const int nrow = P.n;
+  const int K = P.K;
+  const int64_t ngroups = (n + PPW - 1) / PPW;
+  const int grp = lane / G;
+  const int row = lane % G;
+  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+
+  for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb) {
+    unsigned act_mask = 0;
+#pragma unroll 1
+    for (int q = 0; q < PPW; ++q) {
+      const int64_t pt = g * PPW + q;
+      if (pt >= n) break;
+      if (phase_a<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K,
+                            B.nb + q * (K + 1) * NBF, B.mat + q * L.matsz, B.rhs + q * nrow * NR))
+        act_mask |= 1u << q;
+    }
+    const bool gact = (act_mask >> grp) & 1u;
+    const bool ract = gact && row < nrow;
+    double *mat = B.mat + grp * L.matsz;
+    int rowv = row;
+    __asm__ volatile("" : "+v"(rowv));   // keeps row-dependent LDS addresses out of LICM
+    double a[NMAX];
+    double r[NR];
+    load_rows<NMAX, NR>(mat, B.rhs + grp * nrow * NR, rowv, ract, nrow, a, r);
+    double diag;
+    const bool ok = chol_rows<NMAX, G, NR>(a, r, rowv, grp, nug, diag);
+    double v0, v1, qd0, qd1, w0, w1;
+    epilogue<NMAX, G, SPIN, NR, MSE>(P, a, r, diag, gact, ract, row, mat, B.rbuf + grp * 4, v0, v1,
+                                    qd0, qd1, w0, w1);
+    if (row == 0) {
+      const int64_t pt = g * PPW + grp;
+      if (pt < n) store_point<SPIN>(P, pt, n, gact, ok, v0, v1, qd0, qd1, w0, w1, nug, MSE, out, var);
+    }
+  }
+}
+
+// Escalation pass (paper Sec. 2.4 nugget rule): every point tagged by the main
+// pass is recomputed alone, with n = mu + eps where mu is the smallest shift for
+// which S + mu I factorises (bisection on [n0, rows + 1]; the upper end is
+// positive definite by Gershgorin since |S_ij| <= 1).  Untagged chunks cost one
+// coalesced read of `out` per 64 points.
+template <int NMAX, int G, int SPIN, bool MSE>
+__global__ __launch_bounds__(256) void k_escalate(PlanDev P, const double *__restrict__ map,
+                                                  const double *__restrict__ theta,
+                                                  const double *__restrict__ phi, int64_t n,
+                                                  double *__restrict__ out,
+                                                  double *__restrict__ var, Layout L) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  const int nrow = P.n;
+  const int grp = lane / G;
+  const int row = lane % G;
+  const double nug0 = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+  const int64_t nchunks = (n + WAVE - 1) / WAVE;
+  for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb) {
+    const int64_t p0 = ch * WAVE + lane;
+    const bool tagged = p0 < n && (unsigned long long)__double_as_longlong(out[p0]) == FAIL_BITS;
+    unsigned long long mask = __ballot(tagged);
+    while (mask) {
+      const int bit = __ffsll((long long)mask) - 1;
+      mask &= mask - 1ull;
+      const int64_t pt = ch * WAVE + bit;
+      const bool found = phase_a<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs,
+                                           B.sel, B.nb, B.mat, B.rhs);
+      const bool gact = found && grp == 0;
+      const bool ract = gact && row < nrow;
+      double a[NMAX];
+      double r[NR];
+      double diag;
+      double lo = nug0, hi = (double)nrow + 1.0;
+#pragma unroll 1
+      for (int it = 0; it < 64; ++it) {
+        const double mu = 0.5 * (lo + hi);
+        load_rows<NMAX, NR>(B.mat, B.rhs, row, ract, nrow, a, r);
+        const bool ok2 = __all(chol_rows<NMAX, G, NR>(a, r, row, grp, mu, diag) || !gact);
+        if (ok2) hi = mu; else lo = mu;
+      }
+      double nug = hi + P.eps;
+      bool ok = false;
+#pragma unroll 1
+      for (int it = 0; it < 8 && !ok; ++it) {
+        load_rows<NMAX, NR>(B.mat, B.rhs, row, ract, nrow, a, r);
+        ok = __all(chol_rows<NMAX, G, NR>(a, r, row, grp, nug, diag) || !gact);
+        if (!ok) nug *= 2.0;
+      }
+      double v0, v1, qd0, qd1, w0, w1;
+      epilogue<NMAX, G, SPIN, NR, MSE>(P, a, r, diag, gact, ract, row, B.mat, B.rbuf, v0, v1, qd0,
+                                      qd1, w0, w1);
+      if (lane == 0) {
+        atomicAdd(P.counters + CNT_NUGGET_ESC, 1ull);
+        store_point<SPIN>(P, pt, n, gact, ok, v0, v1, qd0, qd1, w0, w1, nug, MSE, out, var);
+      }
+    }
+  }
+}
+
+// Stencil only (a2/a3): K nearest pixel indices per target.
+__global__ __launch_bounds__(256) void k_stencil(PlanDev P, const double *__restrict__ theta,
+                                                 const double *__restrict__ phi, int64_t n,
+                                                 int64_t *__restrict__ idx, Layout L) {
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  char *wb = lds + wave * L.wave_bytes;
+  double *cu = (double *)(wb + L.off_cu);
+  int *ci = (int *)(wb + L.off_ci);
+  RingSpan *rs = (RingSpan *)(wb + L.off_rings);
+  int *sel = (int *)(wb + L.off_sel);
+  const int K = P.K;
+  for (int64_t pt = (int64_t)blockIdx.x * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb) {
+    const double th = theta[pt], ph = phi[pt];
+    const bool good = (th >= 0.0) && (th <= PI_D) && isfinite(ph);
+    bool found = false;
+    if (good) found = knn_search(P, th, ph, lane, cu, ci, rs, sel);
+    for (int k = lane; k < K; k += WAVE) idx[pt * K + k] = found ? (int64_t)sel[k] : -1;
+    wave_lds_sync();
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+struct DevLimits {
+  int ncu = 0;
+  int lds_max = 0;
+};
+
+static DevLimits device_limits() {
+  static std::mutex mu;
+  static std::map<int, DevLimits> cache;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  DevLimits d;
+  hipDeviceGetAttribute(&d.ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  cache[dev] = d;
+  return d;
+}
+
+template <int NMAX, int G, int SPIN, bool MSE>
+static int launch_t(const Plan *p, const double *map, const double *theta, const double *phi,
+                    int64_t n, double *out, double *var, hipStream_t s) {
+  constexpr int PPW = WAVE / G;
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  const DevLimits lim = device_limits();
+  const int nrow = p->d.n;
+  Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, nrow, PPW, G, NR);
+  int wpb = MAX_WPB;
+  while (wpb > 1 && L.tab_bytes + wpb * L.wave_bytes > lim.lds_max) --wpb;
+  const int lds = L.tab_bytes + wpb * L.wave_bytes;
+  if (lds > lim.lds_max) {
+    set_error("plan needs more LDS than the device offers (reduce K or the table size)");
+    return FLINTS_ELIMIT;
+  }
+  auto kern = k_interp64<NMAX, G, SPIN, MSE>;
+  hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  int occ = 0;
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, wpb * WAVE, lds);
+  if (occ < 1) occ = 1;
+  const int64_t ngroups = (n + PPW - 1) / PPW;
+  int64_t blocks = std::min<int64_t>((ngroups + wpb - 1) / wpb, (int64_t)lim.ncu * occ);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(wpb * WAVE), lds, s, p->d, map, theta,
+                     phi, n, out, var, L);
+  auto esc = k_escalate<NMAX, G, SPIN, MSE>;
+  hipFuncSetAttribute((const void *)esc, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const int64_t eblocks = std::min<int64_t>(((n + WAVE - 1) / WAVE + wpb - 1) / wpb, (int64_t)lim.ncu * 4);
+  hipLaunchKernelGGL(esc, dim3((unsigned)std::max<int64_t>(eblocks, 1)), dim3(wpb * WAVE), lds, s, p->d,
+                     map, theta, phi, n, out, var, L);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("interpolation kernel launch failed: ") + hipGetErrorString(e));
+    return FLINTS_EDEVICE;
+  }
+  return FLINTS_OK;
+}
+
+template <int SPIN, bool MSE>
+static int launch_spin(const Plan *p, const double *map, const double *theta, const double *phi,
+                       int64_t n, double *out, double *var, hipStream_t s) {
+  const int nrow = p->d.n;
+  if (nrow <= 16) return launch_t<16, 16, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
+  if (nrow <= 32) return launch_t<32, 32, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
+  if (nrow <= 48) return launch_t<48, 64, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
+  return launch_t<64, 64, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
+}
+
+int launch_interpolate(const Plan *p, const double *map, const double *theta, const double *phi,
+                       int64_t n, double *out, double *var, hipStream_t s) {
+  if (n == 0) return FLINTS_OK;
+  const bool mse = (p->d.var_kind == FLINTS_VAR_MSE) && var != nullptr;
+  if (p->d.spin == 0)
+    return mse ? launch_spin<0, true>(p, map, theta, phi, n, out, var, s)
+               : launch_spin<0, false>(p, map, theta, phi, n, out, var, s);
+  return mse ? launch_spin<2, true>(p, map, theta, phi, n, out, var, s)
+             : launch_spin<2, false>(p, map, theta, phi, n, out, var, s);
+}
+
+int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_t n, int64_t *idx,
+                   hipStream_t s) {
+  if (n == 0) return FLINTS_OK;
+  const DevLimits lim = device_limits();
+  Layout L = make_layout(0, 1, p->d.K, 1, 1, 64, 2);
+  const int wpb = MAX_WPB;
+  const int lds = wpb * L.wave_bytes;
+  hipFuncSetAttribute((const void *)k_stencil, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  int64_t blocks = std::min<int64_t>((n + wpb - 1) / wpb, (int64_t)lim.ncu * 8);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_stencil, dim3((unsigned)blocks), dim3(wpb * WAVE), lds, s, p->d, theta,
+                     phi, n, idx, L);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("stencil kernel launch failed: ") + hipGetErrorString(e));
+    return FLINTS_EDEVICE;
+  }
+  return FLINTS_OK;
+}
+
+}  // namespace flints

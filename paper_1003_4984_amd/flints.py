@@ -1,0 +1,213 @@
+"""ctypes binding of libflints.so (argument marshalling only).
+
+Every step of the interpolation runs in the HIP kernels behind the C ABI; torch
+tensors are used for device memory and streams.  There is no CPU fallback: if the
+library is missing, every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflints.so")
+
+FP64, FP32_IR = 0, 1
+S2_FULL, S2_PAPER = 0, 1
+NUG_ALWAYS, NUG_ON_FAILURE = 0, 1
+VAR_PAPER, VAR_MSE = 0, 1
+
+_lib = None
+
+
+class FlintsError(RuntimeError):
+    pass
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("spin2_mode", ctypes.c_int),
+                ("nugget", ctypes.c_int), ("var_kind", ctypes.c_int),
+                ("table_tol", ctypes.c_double), ("pivot_ratio_min", ctypes.c_double),
+                ("refine_tol", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int64), ("lmax", ctypes.c_int), ("K", ctypes.c_int),
+                ("spin", ctypes.c_int), ("ntab", ctypes.c_int), ("table_step", ctypes.c_double),
+                ("table_smax", ctypes.c_double), ("table_err", ctypes.c_double),
+                ("sigma2", ctypes.c_double), ("search_r0", ctypes.c_double),
+                ("search_rcap", ctypes.c_double), ("nugget_eps", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("bad_inputs", ctypes.c_int64), ("nugget_escalations", ctypes.c_int64),
+                ("clamped_vars", ctypes.c_int64), ("fp64_fallbacks", ctypes.c_int64),
+                ("search_failures", ctypes.c_int64), ("table_range", ctypes.c_int64)]
+
+
+EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
+           "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
+           "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error"]
+
+
+def load_library(path=LIB_PATH):
+    """Load libflints.so and declare its signatures (no device work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FlintsError(f"{path} is not built; run `python -m paper_1003_4984_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, c_int, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+    lib.flints_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+    lib.flints_default_opts.restype = None
+    lib.flints_plan.argtypes = [i64, c_int, ctypes.POINTER(ctypes.c_double), c_int, c_int]
+    lib.flints_plan.restype = vp
+    lib.flints_plan_ex.argtypes = [i64, c_int, ctypes.POINTER(ctypes.c_double), c_int, c_int,
+                                   ctypes.POINTER(_Opts)]
+    lib.flints_plan_ex.restype = vp
+    lib.flints_interpolate.argtypes = [vp, dp, dp, dp, i64, dp, dp, vp]
+    lib.flints_interpolate.restype = c_int
+    lib.flints_stencil.argtypes = [vp, dp, dp, i64, dp, vp]
+    lib.flints_stencil.restype = c_int
+    lib.flints_table_eval.argtypes = [vp, dp, i64, dp, vp]
+    lib.flints_table_eval.restype = c_int
+    lib.flints_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    lib.flints_plan_info.restype = c_int
+    lib.flints_plan_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+    lib.flints_plan_stats.restype = c_int
+    lib.flints_plan_reset_stats.argtypes = [vp]
+    lib.flints_plan_reset_stats.restype = c_int
+    lib.flints_plan_destroy.argtypes = [vp]
+    lib.flints_plan_destroy.restype = None
+    lib.flints_last_error.argtypes = []
+    lib.flints_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _err(lib):
+    return lib.flints_last_error().decode(errors="replace")
+
+
+def _check(lib, rc, what):
+    if rc != 0:
+        raise FlintsError(f"{what} failed ({rc}): {_err(lib)}")
+
+
+def _ptr(t, name, dtype=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise FlintsError(f"{name} must be a CUDA (HIP) torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise FlintsError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise FlintsError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A FLINTS plan: tabulated correlation function for (nside, lmax, C_l, K, spin)."""
+
+    def __init__(self, nside, lmax, cl, K, spin, precision=FP64, spin2_mode=S2_FULL,
+                 nugget=NUG_ALWAYS, var_kind=VAR_PAPER, table_tol=0.0,
+                 pivot_ratio_min=0.0, refine_tol=0.0):
+        lib = load_library()
+        cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64).ravel())
+        need = (lmax + 1) * (1 if spin == 0 else 2)
+        if cl.size != need:
+            raise FlintsError(f"cl must hold {need} values for spin {spin}, lmax {lmax}")
+        o = _Opts()
+        lib.flints_default_opts(ctypes.byref(o))
+        o.precision, o.spin2_mode, o.nugget, o.var_kind = precision, spin2_mode, nugget, var_kind
+        o.table_tol, o.pivot_ratio_min, o.refine_tol = table_tol, pivot_ratio_min, refine_tol
+        h = lib.flints_plan_ex(int(nside), int(lmax), cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               int(K), int(spin), ctypes.byref(o))
+        if not h:
+            raise FlintsError(f"flints_plan failed: {_err(lib)}")
+        self._lib, self._h = lib, ctypes.c_void_p(h)
+        self.nside, self.lmax, self.K, self.spin = int(nside), int(lmax), int(K), int(spin)
+        self.npix = 12 * self.nside * self.nside
+        self.nfield = 1 if spin == 0 else 2
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = _Info()
+        _check(self._lib, self._lib.flints_plan_info(self._h, ctypes.byref(i)), "flints_plan_info")
+        return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    def stats(self):
+        s = _Stats()
+        _check(self._lib, self._lib.flints_plan_stats(self._h, ctypes.byref(s)), "flints_plan_stats")
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def reset_stats(self):
+        _check(self._lib, self._lib.flints_plan_reset_stats(self._h), "flints_plan_reset_stats")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.flints_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def interpolate(plan, map_, theta, phi, out=None, var=None, want_var=True, stream=None):
+    """Interpolate `map_` (device float64, RING; spin 2: Q plane then U plane)."""
+    import torch
+    n = theta.numel()
+    if phi.numel() != n:
+        raise FlintsError("theta and phi must have the same length")
+    if map_.numel() != plan.npix * plan.nfield:
+        raise FlintsError(f"map must hold {plan.npix * plan.nfield} values")
+    if out is None:
+        out = torch.empty(plan.nfield * n, dtype=torch.float64, device=theta.device)
+    if var is None and want_var:
+        var = torch.empty(plan.nfield * n, dtype=torch.float64, device=theta.device)
+    if out.numel() != plan.nfield * n or (var is not None and var.numel() != plan.nfield * n):
+        raise FlintsError("out/var have the wrong size")
+    lib = plan._lib
+    rc = lib.flints_interpolate(plan.handle, _ptr(map_, "map", torch.float64),
+                                _ptr(theta, "theta", torch.float64), _ptr(phi, "phi", torch.float64),
+                                int(n), _ptr(out, "out", torch.float64),
+                                _ptr(var, "var", torch.float64), _stream(stream))
+    _check(lib, rc, "flints_interpolate")
+    return out, var
+
+
+def stencil(plan, theta, phi, stream=None):
+    import torch
+    n = theta.numel()
+    idx = torch.empty((n, plan.K), dtype=torch.int64, device=theta.device)
+    rc = plan._lib.flints_stencil(plan.handle, _ptr(theta, "theta", torch.float64),
+                                  _ptr(phi, "phi", torch.float64), int(n),
+                                  _ptr(idx, "idx", torch.int64), _stream(stream))
+    _check(plan._lib, rc, "flints_stencil")
+    return idx
+
+
+def table_eval(plan, s, stream=None):
+    import torch
+    n = s.numel()
+    nf = plan.nfield
+    out = torch.empty((n, nf), dtype=torch.float64, device=s.device)
+    rc = plan._lib.flints_table_eval(plan.handle, _ptr(s, "s", torch.float64), int(n),
+                                     _ptr(out, "out", torch.float64), _stream(stream))
+    _check(plan._lib, rc, "flints_table_eval")
+    return out

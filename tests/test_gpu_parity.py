@@ -1,0 +1,208 @@
+"""Parity of the HIP path with the FP64 oracle (element by element, seeded inputs).
+
+Tolerances (FP64 against FP64): values within 1e-8 of the rms map value,
+variances within 1e-4 relative + 1e-9 sigma0^2 absolute.  Both sides are double
+precision; the GPU interpolates a cubic table accurate to ~1e-12 of zeta(0)
+while the oracle sums the series per pair, and the variance 1 - b^T S^-1 b is a
+cancellation, so its relative tolerance is looser than the values'.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1003_4984_amd as fl
+from oracle import correlation, healpix, kriging
+from workload import configs, spectra, synth, seeds
+
+from _gpu_helpers import dev, gpu_stencil, reconcile_stencils, run_gpu, compare
+
+pytestmark = pytest.mark.gpu
+
+VAL_TOL = 1e-8
+VAR_REL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def cfg1(gpu_ok):
+    return configs.build(1)
+
+
+def test_table_matches_oracle(gpu_ok):
+    lmax = 256
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    p0 = fl.Plan(128, lmax, tt, 16, 0)
+    p2 = fl.Plan(128, lmax, np.concatenate([ee, 0.2 * ee]), 16, 2)
+    for p in (p0, p2):
+        info = p.info()
+        assert info["table_err"] < 1e-11
+        s = np.random.default_rng(0).uniform(0, info["table_smax"], 4000)
+        got = fl.table_eval(p, dev(s)).cpu().numpy()
+        u = 2 * s * s
+        if p.spin == 0:
+            ref = correlation.zeta(u, tt)[0] / correlation.zeta(np.zeros(1), tt)[0][0]
+            assert np.max(np.abs(got[:, 0] - ref)) < 1e-11
+        else:
+            xp, xm, xp0 = correlation.xi_pm(u, ee, 0.2 * ee)
+            assert np.max(np.abs(got[:, 0] - xp / xp0)) < 1e-11
+            assert np.max(np.abs(got[:, 1] - xm / xp0)) < 1e-11
+
+
+def test_stencil_cfg1(cfg1):
+    sh = cfg1["shape"]
+    p = fl.Plan(sh["nside"], sh["lmax"], cfg1["cl_tt"], sh["K"], 0)
+    th, ph = cfg1["theta"].numpy(), cfg1["phi"].numpy()
+    sel = configs.parity_subset(1, len(th), 6000)
+    g = gpu_stencil(p, th[sel], ph[sel])
+    o = kriging.stencils(sh["nside"], th[sel], ph[sel], sh["K"])
+    ndiff = reconcile_stencils(sh["nside"], th[sel], ph[sel], g, o)
+    assert ndiff <= 5
+
+
+@pytest.mark.parametrize("nside,K", [(1, 12), (1, 5), (2, 40), (4, 64), (16, 24), (256, 32)])
+def test_stencil_edge_geometry(gpu_ok, nside, K):
+    cl = np.zeros(2 * nside + 3)
+    cl[1:] = 1.0
+    p = fl.Plan(nside, len(cl) - 1, cl, K, 0)
+    rng = np.random.default_rng(nside * 7 + K)
+    th = np.concatenate([np.arccos(rng.uniform(-1, 1, 300)),
+                         [0.0, np.pi, 1e-9, np.pi - 1e-9, np.arccos(2 / 3), np.arccos(-2 / 3), np.pi / 2]])
+    ph = np.concatenate([rng.uniform(-20, 20, 300), [0.0, 1.0, 2 * np.pi, -1e-13, 0.5, 6.2831853, 3.0]])
+    g = gpu_stencil(p, th, ph)
+    o = kriging.stencils(nside, th, ph, K)
+    ndiff = reconcile_stencils(nside, th, ph, g, o)
+    assert ndiff <= 8     # exact symmetric ties (poles, ring starts) resolve by rounding
+
+
+def _oracle_on_gpu_stencil(nside, cl, K, spin, maps, th, ph, g, **kw):
+    o_st = kriging.stencils(nside, th, ph, K)
+    reconcile_stencils(nside, th, ph, g, o_st)
+    return kriging.interpolate(nside, cl, K, spin, maps, th, ph, stencil_idx=g, **kw)
+
+
+def test_parity_cfg1(cfg1):
+    sh = cfg1["shape"]
+    nside, K = sh["nside"], sh["K"]
+    p = fl.Plan(nside, sh["lmax"], cfg1["cl_tt"], K, 0)
+    T = cfg1["maps"]["T"].numpy()
+    th, ph = cfg1["theta"].numpy(), cfg1["phi"].numpy()
+    v_all, var_all = run_gpu(p, T, th, ph)           # the full 49,152-point launch
+    assert np.all(np.isfinite(v_all)) and np.all(var_all >= 0)
+    sel = configs.parity_subset(1, len(th), 5000)
+    g = gpu_stencil(p, th[sel], ph[sel])
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, cfg1["cl_tt"], K, 0, T, th[sel], ph[sel], g)
+    s2 = p.info()["sigma2"]
+    compare(v_all[sel], var_all[sel], vo, varo, VAL_TOL, VAR_REL, 1e-9 * s2)
+    st = p.stats()
+    assert st["bad_inputs"] == 0 and st["search_failures"] == 0 and st["table_range"] == 0
+
+
+@pytest.mark.parametrize("mode", [fl.S2_FULL, fl.S2_PAPER])
+@pytest.mark.parametrize("K", [8, 16, 24, 32])
+def test_parity_spin2(gpu_ok, mode, K):
+    nside, lmax = 64, 160
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    bb = 0.1 * ee
+    rng = seeds.rng(2, K, 0)
+    aT, aE = synth.draw_alm_te(rng, tt, ee, te, lmax)
+    q, u = synth.synth(-aE, 2, nside)
+    q, u = q.numpy(), u.numpy()
+    p = fl.Plan(nside, lmax, np.concatenate([ee, bb]), K, 2, spin2_mode=mode)
+    th, ph = np.arccos(rng.uniform(-1, 1, 1500)), rng.uniform(0, 2 * np.pi, 1500)
+    v, var = run_gpu(p, (q, u), th, ph)
+    g = gpu_stencil(p, th, ph)
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, (ee, bb), K, 2, (q, u), th, ph, g,
+                                         mode="paper" if mode == fl.S2_PAPER else "full")
+    s2 = p.info()["sigma2"]
+    compare(v, var, vo, varo, VAL_TOL, VAR_REL, 1e-9 * s2)
+
+
+@pytest.mark.parametrize("K", [1, 7, 16, 24, 33, 48, 64])
+def test_parity_spin0_K(gpu_ok, K):
+    nside, lmax = 32, 80
+    cl = spectra.cl_config1(lmax, sigma_arcmin=60.0)
+    rng = seeds.rng(1, K, 0)
+    m = synth.synth(synth.draw_alm(rng, cl, lmax), 0, nside).numpy()
+    p = fl.Plan(nside, lmax, cl, K, 0)
+    th, ph = np.arccos(rng.uniform(-1, 1, 1200)), rng.uniform(0, 2 * np.pi, 1200)
+    v, var = run_gpu(p, m, th, ph)
+    g = gpu_stencil(p, th, ph)
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, cl, K, 0, m, th, ph, g)
+    compare(v, var, vo, varo, VAL_TOL, VAR_REL, 1e-9 * p.info()["sigma2"])
+
+
+def test_edge_inputs(gpu_ok):
+    nside, lmax, K = 16, 40, 12
+    cl = spectra.cl_config1(lmax, sigma_arcmin=120.0)
+    m = np.random.default_rng(3).normal(size=healpix.npix(nside))
+    p = fl.Plan(nside, lmax, cl, K, 0)
+    # n = 0 is a no-op
+    out, var = fl.interpolate(p, dev(m), dev(np.zeros(0)), dev(np.zeros(0)))
+    assert out.numel() == 0
+    th = np.array([np.nan, -0.1, np.pi + 1e-9, 0.0, np.pi, 0.5, 1.0])
+    ph = np.array([0.0, 0.0, 0.0, 0.0, 3.0, np.inf, -31.4])
+    p.reset_stats()
+    v, var = run_gpu(p, m, th, ph)
+    assert np.all(np.isnan(v[:3])) and np.all(np.isnan(var[:3])) and np.isnan(v[5])
+    assert np.all(np.isfinite(v[[3, 4, 6]]))
+    assert p.stats()["bad_inputs"] == 4
+    # poles and phi wrap agree with the oracle
+    g = gpu_stencil(p, th[[3, 4, 6]], ph[[3, 4, 6]])
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, cl, K, 0, m, th[[3, 4, 6]], ph[[3, 4, 6]], g)
+    compare(v[[3, 4, 6]], var[[3, 4, 6]], vo, varo, VAL_TOL, VAR_REL, 1e-9 * p.info()["sigma2"])
+    # var may be NULL
+    out, var = fl.interpolate(p, dev(m), dev(th[3:5]), dev(ph[3:5]), want_var=False)
+    assert var is None and np.all(np.isfinite(out.cpu().numpy()))
+
+
+def test_pixel_centres_and_zero_deflection(gpu_ok):
+    nside, lmax, K = 32, 64, 16
+    cl = spectra.cl_config1(lmax, sigma_arcmin=60.0)
+    m = synth.synth(synth.draw_alm(seeds.rng(5, 0, 0), cl, lmax), 0, nside).numpy()
+    p = fl.Plan(nside, lmax, cl, K, 0)
+    th, ph = healpix.pix2ang(nside, np.arange(healpix.npix(nside)))
+    v, var = run_gpu(p, m, th, ph)
+    s2 = p.info()["sigma2"]
+    assert np.max(np.abs(v - m)) < 1e-5 * np.sqrt(s2)
+    assert np.all(var <= p.info()["nugget_eps"] * s2 * (1 + 1e-3) + 1e-12 * s2)
+    assert np.all(var >= 0)
+
+
+def test_nugget_escalation_on_failure(gpu_ok):
+    """Single-l spectrum: S has rank 2l+1 < K, so the paper-literal policy (no
+    nugget unless the factorisation fails) must escalate to -lambda_min + eps.
+    The map is a realisation of that field, so it lies in the range of S (a white
+    map would project onto the null space, where 1/eps amplifies rounding)."""
+    nside, K, L = 16, 20, 3
+    cl = np.zeros(L + 1)
+    cl[L] = 1.0
+    m = synth.synth(synth.draw_alm(seeds.rng(6, 0, 0), cl, L), 0, nside).numpy()
+    p = fl.Plan(nside, L, cl, K, 0, nugget=fl.NUG_ON_FAILURE)
+    rng = np.random.default_rng(6)
+    th, ph = np.arccos(rng.uniform(-1, 1, 200)), rng.uniform(0, 6.28, 200)
+    v, var = run_gpu(p, m, th, ph)
+    assert p.stats()["nugget_escalations"] > 0
+    g = gpu_stencil(p, th, ph)
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, cl, K, 0, m, th, ph, g, nugget="on_failure")
+    # K exceeds the 7 modes, so the field is recovered exactly; the variance is
+    # zero up to rounding amplified by cond(S + eps I) ~ 1/eps (both sides)
+    s2 = p.info()["sigma2"]
+    compare(v, var, vo, varo, 1e-6, 0.0, 2e-7 * s2)
+
+
+@pytest.mark.parametrize("spin", [0, 2])
+def test_var_mse(gpu_ok, spin):
+    nside, lmax, K = 32, 80, 16
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    rng = seeds.rng(3, spin, 0)
+    if spin == 0:
+        m = synth.synth(synth.draw_alm(rng, tt, lmax), 0, nside).numpy()
+        cl, maps, clo = tt, m, tt
+    else:
+        q, u = synth.synth(-synth.draw_alm(rng, ee, lmax), 2, nside)
+        cl, maps, clo = np.concatenate([ee, bb]), (q.numpy(), u.numpy()), (ee, bb)
+    p = fl.Plan(nside, lmax, cl, K, spin, var_kind=fl.VAR_MSE)
+    th, ph = np.arccos(rng.uniform(-1, 1, 500)), rng.uniform(0, 6.28, 500)
+    v, var = run_gpu(p, maps, th, ph)
+    g = gpu_stencil(p, th, ph)
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, clo, K, spin, maps, th, ph, g, var_kind="mse")
+    compare(v, var, vo, varo, VAL_TOL, VAR_REL, 1e-9 * p.info()["sigma2"])

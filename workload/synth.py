@@ -9,8 +9,9 @@ e^{i m phi} d^l_{m,-s}(theta).  With this convention
 The Wigner d_{m, +-s}(theta) are advanced by their three-term l-recurrence, all
 (m, ring) pairs at once, in scaled arithmetic (mantissa x 2^E) so that seeds
 like sin^m(theta/2) that underflow double precision near the poles stay exact.
-Runs on CPU (tests) or on the GPU through torch (large maps); it is input
-generation only, not part of the interpolation path.
+On CPU the recurrences run as torch tensor loops; on a GPU device the Legendre
+stage runs in a small HIP kernel (workload/csrc/synth.hip).  The ring sums over m
+use numpy FFTs in both cases.  Input generation only, not part of the interpolation path.
 """
 import math
 import numpy as np
@@ -149,41 +150,44 @@ def _wigner_sums(coef, s, theta, lmax, device):
     return A, B
 
 
-def _rings_to_map(A, B, s, rg, lmax, device):
-    """Sum over m on every ring with FFTs; returns (re, im) maps in RING order."""
+def _rings_to_map(A, B, s, rg, lmax):
+    """Sum over m on every ring with FFTs (numpy pocketfft: any ring length, no
+    per-length kernel compilation); returns (re, im) numpy maps in RING order."""
+    A = A.cpu().numpy() if isinstance(A, torch.Tensor) else A
+    if B is not None:
+        B = B.cpu().numpy() if isinstance(B, torch.Tensor) else B
     npix = int(rg["first"][-1] + rg["count"][-1])
-    re = torch.zeros(npix, dtype=torch.float64, device=device)
-    im = torch.zeros(npix, dtype=torch.float64, device=device)
+    re = np.zeros(npix)
+    im = np.zeros(npix)
     M = lmax + 1
-    mvec = torch.arange(M, device=device)
-    cm = torch.where(mvec == 0, 0.5, 1.0).to(torch.float64)
+    mvec = np.arange(M)
+    cm = np.where(mvec == 0, 0.5, 1.0)
     counts = rg["count"]
-    # group rings by pixel count (the belt shares one length; caps are mirrored pairs)
+
+    def fold(G, n):
+        """G[..., m] -> sum over m = k (mod n), k = 0..n-1."""
+        pad = (-G.shape[-1]) % n
+        if pad:
+            G = np.concatenate([G, np.zeros(G.shape[:-1] + (pad,), G.dtype)], axis=-1)
+        return G.reshape(G.shape[:-1] + (-1, n)).sum(axis=-2)
+
     for n in np.unique(counts):
+        n = int(n)
         rows = np.nonzero(counts == n)[0]
-        rr = torch.as_tensor(rows, device=device)
-        phi0 = torch.as_tensor(rg["phi0"][rows], dtype=torch.float64, device=device)
-        ph = torch.exp(1j * mvec[None, :].to(torch.float64) * phi0[:, None])      # (nr, M)
-        Ga = (cm[None, :] * A[:, rr].T) * ph
-        Gb = (cm[None, :] * B[:, rr].T) * ph if B is not None else None
-        k = (mvec % int(n))
-        Fa = torch.zeros(len(rows), int(n), dtype=torch.complex128, device=device)
-        Fa.index_add_(1, k, Ga)
-        ya = torch.fft.ifft(Fa, dim=1) * int(n)
-        if Gb is not None:
-            Fb = torch.zeros(len(rows), int(n), dtype=torch.complex128, device=device)
-            Fb.index_add_(1, k, Gb)
-            yb = torch.fft.ifft(Fb, dim=1) * int(n)
-        if s % 2 == 0:
-            r_part = ya.real
-            i_part = yb.imag if Gb is not None else torch.zeros_like(ya.real)
-        else:
-            r_part = yb.real
-            i_part = ya.imag
-        first = torch.as_tensor(rg["first"][rows], device=device)
-        pix = (first[:, None] + torch.arange(int(n), device=device)[None, :]).flatten()
-        re[pix] = r_part.flatten()
-        im[pix] = i_part.flatten()
+        for c0 in range(0, len(rows), 512):
+            rr = rows[c0:c0 + 512]
+            ph = np.exp(1j * mvec[None, :] * rg["phi0"][rr][:, None]) * cm[None, :]
+            ya = np.fft.ifft(fold(A[:, rr].T * ph, n), axis=-1) * n
+            yb = np.fft.ifft(fold(B[:, rr].T * ph, n), axis=-1) * n if B is not None else None
+            if s % 2 == 0:
+                r_part = ya.real
+                i_part = yb.imag if yb is not None else 0.0 * ya.real
+            else:
+                r_part = yb.real
+                i_part = ya.imag
+            pix = (rg["first"][rr][:, None] + np.arange(n)[None, :]).ravel()
+            re[pix] = r_part.ravel()
+            im[pix] = i_part.ravel()
     return re, im
 
 
@@ -198,6 +202,12 @@ def synth(elm, s, nside, device="cpu"):
     norm = np.sqrt((2 * ell + 1) / (4 * np.pi)) * (-1.0) ** s
     coef = elm * norm[:, None]
     coef[:s] = 0.0
-    A, B = _wigner_sums(coef, s, rg["theta"], lmax, device)
-    re, im = _rings_to_map(A, B, s, rg, lmax, device)
+    if str(device).startswith("cuda"):
+        from .gpu_synth import wigner_sums
+        A, B = wigner_sums(coef, s, rg["theta"], lmax, device)
+    else:
+        A, B = _wigner_sums(coef, s, rg["theta"], lmax, device)
+    re, im = _rings_to_map(A, B, s, rg, lmax)
+    re = torch.as_tensor(re, device=device)
+    im = torch.as_tensor(im, device=device)
     return re if s == 0 else (re, im)
