@@ -8,7 +8,9 @@ its order (Sec. 2.5, "The interpolation algorithm"), with the stencil rule read 
  2. the correlation function (oracle.correlation, exact per pair, no table);
  3. the neighbour covariance S (Eq. fundamental_variance / variance_matrix for
     spin 0, Eq. v_spins for spin s), regularised S + n I (Sec. 2.4, nugget),
-    factorised S + n I = L L^T and L inverted directly (Sec. 2.4);
+    factorised S + n I = L L^T (Sec. 2.4) and solved by forward and back
+    substitution (the paper inverts L; same result in exact arithmetic, see
+    _solve_via_cholesky);
  4. the neighbours of each direction (K nearest, ties to the smaller index);
  5. the weighted sum, Eq. best_temperature_field (spin 0) / Eq. major_eq (spin 2);
  6. the kriging variance, Eq. gaussvar / Eq. gaussvar_pol (exponent read as 2).
@@ -122,11 +124,37 @@ def _cholesky_with_nugget(S, policy, eps=EPS_F64):
     return L, nug
 
 
-def _inverse_via_cholesky(S, policy):
+def _forward(L, B):
+    """Solve L Y = B for lower-triangular L by forward substitution (batched)."""
+    Y = np.zeros(np.broadcast_shapes(B.shape, B.shape), dtype=np.result_type(L, B))
+    n = L.shape[-1]
+    for i in range(n):
+        acc = B[:, i, :] - np.einsum("bk,bkm->bm", L[:, i, :i], Y[:, :i, :])
+        Y[:, i, :] = acc / L[:, i, i][:, None]
+    return Y
+
+
+def _backward_h(L, Y):
+    """Solve L^H X = Y (L lower-triangular) by back substitution (batched)."""
+    X = np.zeros_like(Y)
+    n = L.shape[-1]
+    LH = np.conj(np.swapaxes(L, -1, -2))
+    for i in range(n - 1, -1, -1):
+        acc = Y[:, i, :] - np.einsum("bk,bkm->bm", LH[:, i, i + 1:], X[:, i + 1:, :])
+        X[:, i, :] = acc / LH[:, i, i][:, None]
+    return X
+
+
+def _solve_via_cholesky(S, rhs, policy):
+    """(S + n I)^-1 rhs with S + n I = L L^H, by forward and back substitution.
+
+    rhs: (B, n, m).  The paper inverts L explicitly (Sec. 2.4); in exact
+    arithmetic that is the same, but at the high-resolution end (N_side 4096)
+    the variance 1 - b^T S^-1 b is ~1e-8 and an explicit inverse loses it to
+    rounding (error ~ eps cond(S)), while substitution is backward stable.
+    """
     L, nug = _cholesky_with_nugget(S, policy)
-    Linv = np.linalg.inv(L)
-    Sinv = np.conj(np.swapaxes(Linv, -1, -2)) @ Linv
-    return Sinv, nug
+    return _backward_h(L, _forward(L, rhs)), nug
 
 
 # --------------------------------------------------------------------------- spin 0
@@ -145,8 +173,8 @@ def krige_spin0(t_theta, t_phi, nvec, vals, cl, nugget="always", var_kind="paper
     V = z / sigma2                                             # Eq. fundamental_variance
     S = V[:, 1:, 1:]
     b = V[:, 1:, 0]
-    Sinv, nug = _inverse_via_cholesky(S, nugget)
-    w = np.einsum("bij,bj->bi", Sinv, b)
+    w, nug = _solve_via_cholesky(S, b[:, :, None], nugget)
+    w = w[:, :, 0]                                             # w = (S + n I)^-1 b
     value = np.einsum("bi,bi->b", w, vals)                    # Eq. best_temperature_field
     var = sigma2 * (1.0 - np.einsum("bi,bi->b", b, w))        # Eq. gaussvar
     if var_kind == "mse":
@@ -188,9 +216,10 @@ def krige_spin2(t_theta, t_phi, nvec, et_n, ep_n, qvals, uvals, cl_ee, cl_bb,
         Gn = G / xp0                                           # Eq. v_spins
         S = Gn[:, 1:, 1:]
         g = Gn[:, 0, 1:]                                       # <P_0 P_b*> / xi_+(0)
-        Sinv, nug = _inverse_via_cholesky(S, nugget)
+        # row vector g^T S^-1 = (S^-1 g^*)^* ^T for Hermitian S
+        wc, nug = _solve_via_cholesky(S, np.conj(g)[:, :, None], nugget)
+        wgt = np.conj(wc[:, :, 0])
         p = qvals + 1j * uvals
-        wgt = np.einsum("bj,bji->bi", g, Sinv)                 # row vector g^T S^-1
         Phat = np.einsum("bi,bi->b", wgt, p)                   # Eq. major_eq
         quad = np.einsum("bi,bi->b", wgt, np.conj(g)).real
         varP = xp0 * (1.0 - quad)                              # Eq. gaussvar_pol
@@ -212,9 +241,8 @@ def krige_spin2(t_theta, t_phi, nvec, et_n, ep_n, qvals, uvals, cl_ee, cl_bb,
     C[:, K:, K:] = CUU[:, 1:, 1:]
     cQ = np.concatenate([CQQ[:, 1:, 0], CUQ[:, 1:, 0]], axis=1)   # Cov(x, Q_0)
     cU = np.concatenate([CQU[:, 1:, 0], CUU[:, 1:, 0]], axis=1)   # Cov(x, U_0)
-    Cinv, nug = _inverse_via_cholesky(C, nugget)
-    wQ = np.einsum("bij,bj->bi", Cinv, cQ)
-    wU = np.einsum("bij,bj->bi", Cinv, cU)
+    W, nug = _solve_via_cholesky(C, np.stack([cQ, cU], axis=-1), nugget)
+    wQ, wU = W[:, :, 0], W[:, :, 1]
     x = np.concatenate([qvals, uvals], axis=1)
     val = np.stack([np.einsum("bi,bi->b", wQ, x), np.einsum("bi,bi->b", wU, x)], axis=-1)
     s2 = 0.5 * xp0
@@ -233,6 +261,8 @@ def interpolate(nside, cl, K, spin, maps, theta, phi, mode="full", nugget="alway
 
     spin 0: cl = C^TT[0..lmax], maps = T[npix];  returns value (n,), var (n,).
     spin 2: cl = (C^EE, C^BB), maps = (Q[npix], U[npix]);  returns (n, 2), (n, 2).
+    A map may also be given as a function pix -> values (for maps too large to
+    hold on the host; only the stencil pixels are read).
     Directions with theta outside [0, pi] or non-finite give NaN.
     Also returns the stencils (n, K) used.
     """
@@ -253,14 +283,14 @@ def interpolate(nside, cl, K, spin, maps, theta, phi, mode="full", nugget="alway
         idx = gi[s:s + batch]
         st = stencil_idx[idx]
         nv, et, ep = _pixel_frames(nside, st)
+        take = lambda m: m(st) if callable(m) else np.asarray(m)[st]
         if spin == 0:
-            v, w, _ = krige_spin0(theta[idx], phi[idx], nv, np.asarray(maps)[st], cl,
+            v, w, _ = krige_spin0(theta[idx], phi[idx], nv, take(maps), cl,
                                   nugget=nugget, var_kind=var_kind)
         else:
             Q, U = maps
-            v, w, _ = krige_spin2(theta[idx], phi[idx], nv, et, ep, np.asarray(Q)[st],
-                                  np.asarray(U)[st], cl[0], cl[1], mode=mode,
-                                  nugget=nugget, var_kind=var_kind)
+            v, w, _ = krige_spin2(theta[idx], phi[idx], nv, et, ep, take(Q), take(U),
+                                  cl[0], cl[1], mode=mode, nugget=nugget, var_kind=var_kind)
         val[idx] = v
         var[idx] = w
     return val, var, stencil_idx
