@@ -31,11 +31,14 @@
 #include <cstring>
 #include <mutex>
 #include <map>
+#include <tuple>
+#include <utility>
 
 namespace flints {
 
 constexpr int WAVE = 64;
-constexpr int MAX_WPB = 4;
+constexpr int MAX_WPB = 8;      // waves per block of the interpolation kernels (launch bound 512)
+constexpr int STENCIL_WPB = 4;  // waves per block of the stencil kernel (launch bound 256)
 constexpr int CAND_CAP = 320;
 constexpr int NBF = 10;  // doubles per neighbour record
 constexpr double PI_D = 3.14159265358979323846;
@@ -114,21 +117,32 @@ struct Layout {
 
 static inline int al16(int x) { return (x + 15) & ~15; }
 
+// Per-wave LDS: the stencils of the wave's points, then a region used first by
+// the K-nearest search (candidates, ring spans) and afterwards by the assembly
+// (one neighbour-record slot, the packed systems and right-hand sides of all
+// PPW points).  The search of every point of the group runs before any
+// assembly, so the two uses never overlap.
 static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int G, int NR) {
+  (void)G;
   Layout L;
   L.tab_bytes = al16(ntab * nf * 8);
   int o = 0;
-  L.off_cu = o;    o = al16(o + (CAND_CAP + 4) * 8);
-  L.off_ci = o;    o = al16(o + (CAND_CAP + 4) * 4);
-  L.off_rings = o; o = al16(o + WAVE * (int)sizeof(RingSpan));
   L.off_sel = o;   o = al16(o + ppw * K * 4);
-  L.off_nb = o;    o = al16(o + ppw * (K + 1) * NBF * 8);
+  const int u0 = o;
+  // search view
+  int s = u0;
+  L.off_cu = s;    s = al16(s + (CAND_CAP + 4) * 8);
+  L.off_ci = s;    s = al16(s + (CAND_CAP + 4) * 4);
+  L.off_rings = s; s = al16(s + WAVE * (int)sizeof(RingSpan));
+  // assembly view
+  int a = u0;
+  L.off_nb = a;    a = al16(a + (K + 1) * NBF * 8);
   L.matsz = n * (n + 1) / 2;
-  L.off_mat = o;   o = al16(o + ppw * L.matsz * 8);
-  L.off_rhs = o;   o = al16(o + ppw * n * NR * 8);
-  L.off_col = o;
-  L.off_rbuf = o;  o = al16(o + ppw * 4 * 8);
-  L.wave_bytes = o;
+  L.off_mat = a;   a = al16(a + ppw * L.matsz * 8);
+  L.off_rhs = a;   a = al16(a + ppw * n * NR * 8);
+  L.off_col = a;
+  L.off_rbuf = a;  a = al16(a + ppw * 4 * 8);
+  L.wave_bytes = s > a ? s : a;
   return L;
 }
 
@@ -463,12 +477,11 @@ __device__ inline double group_sum(double v) {
 // these points.
 constexpr unsigned long long FAIL_BITS = 0x7ff80000000f1a7ull;
 
-// Phase A for one point with the whole wave; returns false if the point is
-// invalid or its stencil was not found.
-template <int SPIN, int NR>
-__device__ inline bool phase_a(const PlanDev &P, const double *tab, const double *__restrict__ map,
-                               double th, double ph, int lane, double *cu, int *ci, RingSpan *rs,
-                               int *sel, double *nb, double *mat, double *rhs) {
+// Phase A, first half, for one point with the whole wave: validity and the
+// K-nearest search.  Returns false if the point is invalid or its stencil was
+// not found.
+__device__ inline bool phase_a_search(const PlanDev &P, double th, double ph, int lane, double *cu,
+                                      int *ci, RingSpan *rs, int *sel) {
   const bool good = (th >= 0.0) && (th <= PI_D) && isfinite(ph);
   if (!good) {
     if (lane == 0) atomicAdd(P.counters + CNT_BAD_INPUT, 1ull);
@@ -478,9 +491,16 @@ __device__ inline bool phase_a(const PlanDev &P, const double *tab, const double
     if (lane == 0) atomicAdd(P.counters + CNT_SEARCH_FAIL, 1ull);
     return false;
   }
+  return true;
+}
+
+// Phase A, second half: neighbour records and the covariance assembly.
+template <int SPIN, int NR>
+__device__ inline void phase_a_build(const PlanDev &P, const double *tab,
+                                     const double *__restrict__ map, double th, double ph, int lane,
+                                     const int *sel, double *nb, double *mat, double *rhs) {
   neighbour_records<SPIN>(P, th, ph, lane, sel, nb, map);
   assemble<SPIN, NR>(P, tab, nb, lane, mat, rhs);
-  return true;
 }
 
 struct WaveBufs {
@@ -600,7 +620,7 @@ __device__ inline void epilogue(const PlanDev &P, const double (&a)[NMAX], const
 // Main pass over all targets.  MSE adds the MSE variance; a factorisation that
 // fails (non-positive pivot) leaves a tagged NaN for the escalation pass.
 template <int NMAX, int G, int SPIN, bool MSE>
-__global__ __launch_bounds__(256) void k_interp64(PlanDev P, const double *__restrict__ map,
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp64(PlanDev P, const double *__restrict__ map,
                                                   const double *__restrict__ theta,
                                                   const double *__restrict__ phi, int64_t n,
                                                   double *__restrict__ out,
@@ -627,9 +647,15 @@ __global__ __launch_bounds__(256) void k_interp64(PlanDev P, const double *__res
     for (int q = 0; q < PPW; ++q) {
       const int64_t pt = g * PPW + q;
       if (pt >= n) break;
-      if (phase_a<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K,
-                            B.nb + q * (K + 1) * NBF, B.mat + q * L.matsz, B.rhs + q * nrow * NR))
+      if (phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K))
         act_mask |= 1u << q;
+    }
+#pragma unroll 1
+    for (int q = 0; q < PPW; ++q) {
+      if (!((act_mask >> q) & 1u)) continue;
+      const int64_t pt = g * PPW + q;
+      phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel + q * K, B.nb,
+                              B.mat + q * L.matsz, B.rhs + q * nrow * NR);
     }
     const bool gact = (act_mask >> grp) & 1u;
     const bool ract = gact && row < nrow;
@@ -657,7 +683,7 @@ __global__ __launch_bounds__(256) void k_interp64(PlanDev P, const double *__res
 // positive definite by Gershgorin since |S_ij| <= 1).  Untagged chunks cost one
 // coalesced read of `out` per 64 points.
 template <int NMAX, int G, int SPIN, bool MSE>
-__global__ __launch_bounds__(256) void k_escalate(PlanDev P, const double *__restrict__ map,
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate(PlanDev P, const double *__restrict__ map,
                                                   const double *__restrict__ theta,
                                                   const double *__restrict__ phi, int64_t n,
                                                   double *__restrict__ out,
@@ -683,8 +709,9 @@ __global__ __launch_bounds__(256) void k_escalate(PlanDev P, const double *__res
       const int bit = __ffsll((long long)mask) - 1;
       mask &= mask - 1ull;
       const int64_t pt = ch * WAVE + bit;
-      const bool found = phase_a<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs,
-                                           B.sel, B.nb, B.mat, B.rhs);
+      const bool found = phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel);
+      if (found)
+        phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel, B.nb, B.mat, B.rhs);
       const bool gact = found && grp == 0;
       const bool ract = gact && row < nrow;
       double a[NMAX];
@@ -718,7 +745,7 @@ __global__ __launch_bounds__(256) void k_escalate(PlanDev P, const double *__res
 }
 
 // Stencil only (a2/a3): K nearest pixel indices per target.
-__global__ __launch_bounds__(256) void k_stencil(PlanDev P, const double *__restrict__ theta,
+__global__ __launch_bounds__(STENCIL_WPB * WAVE) void k_stencil(PlanDev P, const double *__restrict__ theta,
                                                  const double *__restrict__ phi, int64_t n,
                                                  int64_t *__restrict__ idx, Layout L) {
   extern __shared__ double lds_dyn[];
@@ -771,17 +798,40 @@ static int launch_t(const Plan *p, const double *map, const double *theta, const
   const DevLimits lim = device_limits();
   const int nrow = p->d.n;
   Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, nrow, PPW, G, NR);
-  int wpb = MAX_WPB;
-  while (wpb > 1 && L.tab_bytes + wpb * L.wave_bytes > lim.lds_max) --wpb;
-  const int lds = L.tab_bytes + wpb * L.wave_bytes;
-  if (lds > lim.lds_max) {
+  auto kern = k_interp64<NMAX, G, SPIN, MSE>;
+  // waves per block: the count that puts the most waves on a CU given the LDS
+  // (table shared per block) and register limits; cached per configuration
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int>, std::pair<int, int>> cache;
+  int wpb = 0, occ = 0;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    int dev = 0;
+    hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, L.tab_bytes, L.wave_bytes);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      wpb = it->second.first;
+      occ = it->second.second;
+    } else {
+      int best_waves = 0;
+      for (int w = 1; w <= MAX_WPB; ++w) {
+        const int l = L.tab_bytes + w * L.wave_bytes;
+        if (l > lim.lds_max) break;
+        hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, l);
+        int o = 0;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, w * WAVE, l);
+        if (o * w >= best_waves) { best_waves = o * w; wpb = w; occ = o; }
+      }
+      cache[key] = std::make_pair(wpb, occ);
+    }
+  }
+  if (wpb == 0) {
     set_error("plan needs more LDS than the device offers (reduce K or the table size)");
     return FLINTS_ELIMIT;
   }
-  auto kern = k_interp64<NMAX, G, SPIN, MSE>;
+  const int lds = L.tab_bytes + wpb * L.wave_bytes;
   hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  int occ = 0;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, wpb * WAVE, lds);
   if (occ < 1) occ = 1;
   const int64_t ngroups = (n + PPW - 1) / PPW;
   int64_t blocks = std::min<int64_t>((ngroups + wpb - 1) / wpb, (int64_t)lim.ncu * occ);
@@ -827,7 +877,7 @@ int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_
   if (n == 0) return FLINTS_OK;
   const DevLimits lim = device_limits();
   Layout L = make_layout(0, 1, p->d.K, 1, 1, 64, 2);
-  const int wpb = MAX_WPB;
+  const int wpb = STENCIL_WPB;
   const int lds = wpb * L.wave_bytes;
   hipFuncSetAttribute((const void *)k_stencil, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   int64_t blocks = std::min<int64_t>((n + wpb - 1) / wpb, (int64_t)lim.ncu * 8);
