@@ -91,17 +91,22 @@ __device__ inline double readlane_d(double v, int src) {
   return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+__device__ inline float readlane_d(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Value of `v` in row k of this lane's group (groups of G lanes).
-template <int G>
-__device__ inline double group_bcast(double v, int k, int grp) {
-  double r = readlane_d(v, k);
+template <int G, typename T>
+__device__ inline T group_bcast(T v, int k, int grp) {
+  T r = readlane_d(v, k);
 #pragma unroll
   for (int g = 1; g < WAVE / G; ++g) {
-    const double t = readlane_d(v, g * G + k);
+    const T t = readlane_d(v, g * G + k);
     r = (grp == g) ? t : r;
   }
   return r;
 }
+
 
 struct RingSpan {
   double z, s, phi0, dphi;
@@ -429,39 +434,90 @@ __device__ inline void load_rows(const double *mat, const double *rhs, int row, 
   for (int q = 0; q < NR; ++q) r[q] = act ? rhs[row * NR + q] : 0.0;
 }
 
+__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
+__device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
+
 // Right-looking Cholesky of the group's rows (all NMAX steps) with the
-// right-hand sides carried along.  Every lane updates its whole row, so the
-// matrix stays symmetric and the column needed at step k equals row k, held by
-// one lane: pivot, column and the pivot row's right-hand sides are broadcast
-// with readlane (no LDS traffic).  Steps are generated by template recursion so
-// every register index is a compile-time constant.
-template <int NMAX, int G, int NR, int K>
-__device__ __forceinline__ void chol_step(double (&a)[NMAX], double (&r)[NR], int row, int grp,
-                                          double nug, bool &ok, double &mydiag) {
-  const double d = group_bcast<G>(a[K], K, grp) + nug;
-  ok = ok && (d > 0.0);
-  const double rs = rsqrt(d);
-  const double c = a[K] * rs * rs;
+// right-hand sides carried along.  Every active lane updates its whole row, so
+// the trailing matrix stays symmetric and the column needed at step k equals row
+// k, held by one lane: pivot, column and the pivot row's right-hand sides are
+// broadcast with readlane (no LDS traffic).  Rows that have already pivoted do
+// not update, so at the end lane i holds row i of L (columns < i), L_ii, and in
+// its upper half A^(i)_ij = L_ji L_ii (column i of L, scaled): both triangular
+// solves are then register-local (see back_solve).  Steps are generated by
+// template recursion so every register index is a compile-time constant.
+template <typename T, int NMAX, int G, int NR, int K>
+__device__ __forceinline__ void chol_step(T (&a)[NMAX], T (&r)[NR], int row, int grp, T nug,
+                                          bool &ok, T &mydiag) {
+  const T d = group_bcast<G>(a[K], K, grp) + nug;
+  ok = ok && (d > T(0));
+  const T rs = rsqrt_t(d);
+  const T c = (row > K) ? a[K] * rs * rs : T(0);
 #pragma unroll
   for (int j = K + 1; j < NMAX; ++j) a[j] = fma(-c, group_bcast<G>(a[j], K, grp), a[j]);
 #pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    const double yk = group_bcast<G>(r[q], K, grp);
-    r[q] = (row > K) ? fma(-c, yk, r[q]) : r[q];
-  }
-  const double piv = d * rs;
+  for (int q = 0; q < NR; ++q) r[q] = fma(-c, group_bcast<G>(r[q], K, grp), r[q]);
+  const T piv = d * rs;
   if (row == K) mydiag = piv;
-  a[K] = (row == K) ? piv : a[K] * rs;
-  if constexpr (K + 1 < NMAX) chol_step<NMAX, G, NR, K + 1>(a, r, row, grp, nug, ok, mydiag);
+  a[K] = (row == K) ? piv : ((row > K) ? a[K] * rs : a[K]);
+  if constexpr (K + 1 < NMAX) chol_step<T, NMAX, G, NR, K + 1>(a, r, row, grp, nug, ok, mydiag);
 }
 
-template <int NMAX, int G, int NR>
-__device__ __forceinline__ bool chol_rows(double (&a)[NMAX], double (&r)[NR], int row, int grp,
-                                          double nug, double &mydiag) {
+template <int NMAX, int G, int NR, typename T>
+__device__ __forceinline__ bool chol_rows(T (&a)[NMAX], T (&r)[NR], int row, int grp, T nug,
+                                          T &mydiag) {
   bool ok = true;
-  mydiag = 1.0;
-  chol_step<NMAX, G, NR, 0>(a, r, row, grp, nug, ok, mydiag);
+  mydiag = T(1);
+  chol_step<T, NMAX, G, NR, 0>(a, r, row, grp, nug, ok, mydiag);
   return ok;
+}
+
+// Backward substitution L^T w = y after chol_rows: lane i accumulates
+// sum_{k>i} A^(i)_ik w_k = L_ii sum_{k>i} L_ki w_k from its own upper half as the
+// w_k (k descending) are broadcast, then w_i = (y_i - acc_i / L_ii) / L_ii.
+template <typename T, int NMAX, int G, int NW, int K>
+__device__ __forceinline__ void back_step(const T (&a)[NMAX], const T (&y)[NW], T inv, int row,
+                                          int grp, T (&acc)[NW], T (&w)[NW]) {
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const T t = (y[q] - acc[q] * inv) * inv;
+    const T wk = group_bcast<G>(t, K, grp);
+    if (row == K) w[q] = wk;
+    acc[q] = (row < K) ? fma(a[K], wk, acc[q]) : acc[q];
+  }
+  if constexpr (K > 0) back_step<T, NMAX, G, NW, K - 1>(a, y, inv, row, grp, acc, w);
+}
+
+template <int NMAX, int G, int NW, typename T>
+__device__ __forceinline__ void back_solve(const T (&a)[NMAX], const T (&y)[NW], T diag, int row,
+                                           int grp, T (&w)[NW]) {
+  T acc[NW], inv = T(1) / diag;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) { acc[q] = T(0); w[q] = T(0); }
+  back_step<T, NMAX, G, NW, NMAX - 1>(a, y, inv, row, grp, acc, w);
+}
+
+// Forward substitution L t = v with L in the lanes' lower halves (row i holds
+// L_ij, j < i), pivots broadcast in increasing order.
+template <typename T, int NMAX, int G, int NW, int K>
+__device__ __forceinline__ void fwd_step(const T (&a)[NMAX], T (&v)[NW], T inv, int row, int grp,
+                                         T (&t)[NW]) {
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const T tk = group_bcast<G>(v[q] * inv, K, grp);
+    if (row == K) t[q] = tk;
+    v[q] = (row > K) ? fma(-a[K], tk, v[q]) : v[q];
+  }
+  if constexpr (K + 1 < NMAX) fwd_step<T, NMAX, G, NW, K + 1>(a, v, inv, row, grp, t);
+}
+
+template <int NMAX, int G, int NW, typename T>
+__device__ __forceinline__ void fwd_solve(const T (&a)[NMAX], T (&v)[NW], T diag, int row,
+                                          int grp, T (&t)[NW]) {
+  const T inv = T(1) / diag;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) t[q] = T(0);
+  fwd_step<T, NMAX, G, NW, 0>(a, v, inv, row, grp, t);
 }
 
 template <int G>
@@ -472,10 +528,11 @@ __device__ inline double group_sum(double v) {
 }
 
 // ---------------------------------------------------------------- kernel
-// Output value that marks a point whose factorisation failed in the main pass
-// (a quiet NaN with a private payload); the escalation pass recomputes exactly
-// these points.
-constexpr unsigned long long FAIL_BITS = 0x7ff80000000f1a7ull;
+// Output values that tag a point for the fix-up pass (quiet NaNs with private
+// payloads): FP64 factorisation failed (nugget escalation needed), or the FP32
+// factorisation / refinement was rejected (recompute in FP64).
+constexpr unsigned long long FAIL64_BITS = 0x7ff80000000f1a7ull;
+constexpr unsigned long long FAIL32_BITS = 0x7ff80000000f132ull;
 
 // Phase A, first half, for one point with the whole wave: validity and the
 // K-nearest search.  Returns false if the point is invalid or its stencil was
@@ -528,32 +585,172 @@ __device__ inline const double *load_table(char *lds, const PlanDev &P) {
   return (const double *)lds;
 }
 
-// Writes the outputs of point pt from the group reductions (lane row == 0).
+template <int G>
+__device__ inline double group_min(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
+  return v;
+}
+template <int G>
+__device__ inline double group_max(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
+  return v;
+}
+
+// Per-group results handed to store_point.
+struct GroupOut {
+  double v0, v1, qd0, qd1, w0, w1;
+};
+
+// FP64 phase B: factorise S + nI with the right-hand sides carried, then
+// value = y.z and quad = y.y per point (y = L^-1 b, z = L^-1 data); with MSE
+// also |w|^2 for w = L^-T y (register-local backward solve).
+template <int NMAX, int G, int SPIN, int NR, bool MSE>
+__device__ inline bool fp64_phase_b(const double *mat, const double *rhs, int row, int grp,
+                                    bool ract, int nrow, double nug, GroupOut &o) {
+  constexpr int NW = (SPIN == 0) ? 1 : 2;
+  double a[NMAX];
+  double r[NR];
+  load_rows<NMAX, NR>(mat, rhs, row, ract, nrow, a, r);
+  double diag;
+  const bool ok = chol_rows<NMAX, G, NR>(a, r, row, grp, nug, diag);
+  const double inv = 1.0 / diag;
+  const double y0 = ract ? r[0] * inv : 0.0;
+  const double y1 = ract ? r[1] * inv : 0.0;
+  const double y2 = (ract && NR > 2) ? r[NR - 1] * inv : 0.0;
+  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
+  if (SPIN == 0) {
+    o.v0 = group_sum<G>(y0 * y1);
+    o.qd0 = group_sum<G>(y0 * y0);
+  } else {
+    o.v0 = group_sum<G>(y0 * y2);
+    o.v1 = group_sum<G>(y1 * y2);
+    o.qd0 = group_sum<G>(y0 * y0);
+    o.qd1 = group_sum<G>(y1 * y1);
+  }
+  if (MSE) {
+    double yy[NW], w[NW];
+    yy[0] = y0;
+    if (NW > 1) yy[NW - 1] = y1;
+    back_solve<NMAX, G, NW>(a, yy, diag, row, grp, w);
+    o.w0 = group_sum<G>(ract ? w[0] * w[0] : 0.0);
+    if (NW > 1) o.w1 = group_sum<G>(ract ? w[NW - 1] * w[NW - 1] : 0.0);
+  }
+  return ok;
+}
+
+// FP64 residual res = b - (S + nI) w for the NW right-hand sides, S read from the
+// packed system in LDS and w_j broadcast from row j.
+template <int NMAX, int G, int NW, int NR>
+__device__ inline void residual64(const double *mat, const double *rhs, int row_in, bool ract, int nrow,
+                                  double nug, const double (&w)[NW], int grp, double (&res)[NW]) {
+  int row = row_in;
+  __asm__ volatile("" : "+v"(row));   // recompute the row addresses here instead of keeping them live
+#pragma unroll
+  for (int q = 0; q < NW; ++q) res[q] = ract ? rhs[row * NR + q] - nug * w[q] : 0.0;
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    const int idx = (j <= row) ? tri(row) + j : tri(j) + row;
+    const double sij = (ract && j < nrow) ? mat[idx] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) res[q] = fma(-sij, group_bcast<G>(w[q], j, grp), res[q]);
+    if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
+  }
+}
+
+// FP32 + refinement phase B: covariance entries stay FP64 in LDS;
+// S + nI is rounded to FP32 and factorised, w = (S + nI)^-1 b is solved in FP32,
+// one refinement step uses the FP64 residual and an FP32 correction solve, and
+// value / variance use FP64 accumulation with the final FP64 residual r:
+// var = sigma^2 (1 - b.w - w.r) (stationary in w).  The point is rejected (and
+// recomputed in FP64) if the FP32 factorisation fails, if min L_kk / max L_kk is
+// below the pivot-ratio threshold, or if |dw| > refine_tol |w|.
+template <int NMAX, int G, int SPIN, int NR, bool MSE>
+__device__ inline bool fp32_phase_b(const PlanDev &P, const double *mat, const double *rhs, int row_in,
+                                    int grp, bool ract, int nrow, double nug, GroupOut &o) {
+  constexpr int NW = (SPIN == 0) ? 1 : 2;
+  int row = row_in;
+  __asm__ volatile("" : "+v"(row));
+  float a[NMAX];
+  float rb[NW];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    const int idx = (j <= row) ? tri(row) + j : tri(j) + row;
+    a[j] = ract ? ((j < nrow) ? (float)mat[idx] : 0.0f) : (j == row ? 1.0f : 0.0f);
+  }
+#pragma unroll
+  for (int q = 0; q < NW; ++q) rb[q] = ract ? (float)rhs[row * NR + q] : 0.0f;
+  float diag;
+  bool ok = chol_rows<NMAX, G, NW>(a, rb, row, grp, (float)nug, diag);
+  const double dmin = group_min<G>(ract ? (double)diag : 1e300);
+  const double dmax = group_max<G>(ract ? (double)diag : 0.0);
+  ok = ok && (dmin >= P.pivot_ratio_min * dmax);
+  float y[NW], w32[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) y[q] = rb[q] / diag;
+  back_solve<NMAX, G, NW>(a, y, diag, row, grp, w32);
+  double w[NW], res[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) w[q] = ract ? (double)w32[q] : 0.0;
+  residual64<NMAX, G, NW, NR>(mat, rhs, row, ract, nrow, nug, w, grp, res);
+  float rv[NW], t[NW], dw[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) rv[q] = (float)res[q];
+  fwd_solve<NMAX, G, NW>(a, rv, diag, row, grp, t);
+  back_solve<NMAX, G, NW>(a, t, diag, row, grp, dw);
+  double dn = 0.0, wn = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    w[q] = ract ? w[q] + (double)dw[q] : 0.0;
+    dn += ract ? (double)dw[q] * (double)dw[q] : 0.0;
+    wn += w[q] * w[q];
+  }
+  dn = group_sum<G>(dn);
+  wn = group_sum<G>(wn);
+  ok = ok && (dn <= P.refine_tol * P.refine_tol * wn) && isfinite(dn);
+  residual64<NMAX, G, NW, NR>(mat, rhs, row, ract, nrow, nug, w, grp, res);
+  const double d = ract ? rhs[row * NR + NR - 1] : 0.0;
+  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
+  const double b0 = ract ? rhs[row * NR + 0] : 0.0;
+  o.v0 = group_sum<G>(w[0] * d);
+  o.qd0 = group_sum<G>(w[0] * (b0 + res[0]));
+  if (MSE) o.w0 = group_sum<G>(w[0] * w[0]);
+  if (NW > 1) {
+    const double b1 = ract ? rhs[row * NR + 1] : 0.0;
+    o.v1 = group_sum<G>(w[NW - 1] * d);
+    o.qd1 = group_sum<G>(w[NW - 1] * (b1 + res[NW - 1]));
+    if (MSE) o.w1 = group_sum<G>(w[NW - 1] * w[NW - 1]);
+  }
+  return ok;
+}
+
+// Writes the outputs of point pt (called by lane row == 0 of its group).
+// `tag` marks a rejected point for the fix-up pass.
 template <int SPIN>
 __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool gact, bool ok,
-                                   double v0, double v1, double qd0, double qd1, double w0,
-                                   double w1, double nug, bool mse, double *out, double *var) {
+                                   unsigned long long tag, const GroupOut &o, double nug, bool mse,
+                                   double *out, double *var) {
   const double nan = __builtin_nan("");
-  const double fail = __longlong_as_double((long long)FAIL_BITS);
   const double s2 = P.sigma2;
   const bool good = gact && ok;
-  const double bad = (gact && !ok) ? fail : nan;
+  const double bad = (gact && !ok) ? __longlong_as_double((long long)tag) : nan;
   if (SPIN == 0) {
-    double vv = s2 * (1.0 - qd0);
-    if (mse) vv -= s2 * nug * w0;
+    double vv = s2 * (1.0 - o.qd0);
+    if (mse) vv -= s2 * nug * o.w0;
     if (good && vv < 0.0) { atomicAdd(P.counters + CNT_CLAMPED_VAR, 1ull); vv = 0.0; }
-    out[pt] = good ? v0 : bad;
+    out[pt] = good ? o.v0 : bad;
     if (var) var[pt] = good ? vv : nan;
   } else {
-    double vq = s2 * (1.0 - qd0), vu = s2 * (1.0 - qd1);
-    if (mse) { vq -= s2 * nug * w0; vu -= s2 * nug * w1; }
+    double vq = s2 * (1.0 - o.qd0), vu = s2 * (1.0 - o.qd1);
+    if (mse) { vq -= s2 * nug * o.w0; vu -= s2 * nug * o.w1; }
     if (good && (vq < 0.0 || vu < 0.0)) {
       atomicAdd(P.counters + CNT_CLAMPED_VAR, 1ull);
       vq = fmax(vq, 0.0);
       vu = fmax(vu, 0.0);
     }
-    out[pt] = good ? v0 : bad;
-    out[n + pt] = good ? v1 : bad;
+    out[pt] = good ? o.v0 : bad;
+    out[n + pt] = good ? o.v1 : bad;
     if (var) {
       var[pt] = good ? vq : nan;
       var[n + pt] = good ? vu : nan;
@@ -561,65 +758,8 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
   }
 }
 
-// Group epilogue: y = L^-1 b, z = L^-1 data from the carried right-hand sides,
-// value = y.z and quad = y.y per point by group reductions; with MSE also
-// |w|^2 = |L^-T y|^2 by a backward substitution through LDS.
-template <int NMAX, int G, int SPIN, int NR, bool MSE>
-__device__ inline void epilogue(const PlanDev &P, const double (&a)[NMAX], const double (&r)[NR],
-                                double diag, bool gact, bool ract, int row, double *mat,
-                                double *rbuf, double &v0, double &v1, double &qd0, double &qd1,
-                                double &w0, double &w1) {
-  const double inv = 1.0 / diag;
-  const double y0 = ract ? r[0] * inv : 0.0;
-  const double y1 = ract ? r[1] * inv : 0.0;
-  const double y2 = (ract && NR > 2) ? r[NR - 1] * inv : 0.0;
-  v1 = 0.0;
-  qd1 = 0.0;
-  if (SPIN == 0) {
-    v0 = group_sum<G>(y0 * y1);
-    qd0 = group_sum<G>(y0 * y0);
-  } else {
-    v0 = group_sum<G>(y0 * y2);
-    v1 = group_sum<G>(y1 * y2);
-    qd0 = group_sum<G>(y0 * y0);
-    qd1 = group_sum<G>(y1 * y1);
-  }
-  w0 = 0.0;
-  w1 = 0.0;
-  if (MSE) {
-    const int nrow = P.n;
-    if (ract) {
-#pragma unroll
-      for (int j = 0; j < NMAX; ++j)
-        if (j < row) mat[tri(row) + j] = a[j];
-    }
-    wave_lds_sync();
-    double x0 = y0, x1 = y1;
-#pragma unroll 1
-    for (int k = nrow - 1; k >= 0; --k) {
-      if (row == k && gact) {
-        x0 *= inv;
-        x1 *= inv;
-        rbuf[0] = x0;
-        rbuf[1] = x1;
-      }
-      wave_lds_sync();
-      const double b0 = rbuf[0], b1 = rbuf[1];
-      if (gact && row < k) {
-        const double l = mat[tri(k) + row];
-        x0 = fma(-l, b0, x0);
-        x1 = fma(-l, b1, x1);
-      }
-      wave_lds_sync();
-    }
-    w0 = group_sum<G>(ract ? x0 * x0 : 0.0);
-    w1 = group_sum<G>(ract ? x1 * x1 : 0.0);
-  }
-}
-
-// Main pass over all targets.  MSE adds the MSE variance; a factorisation that
-// fails (non-positive pivot) leaves a tagged NaN for the escalation pass.
-template <int NMAX, int G, int SPIN, bool MSE>
+// Main pass over all targets (FP32 selects the FP32 + refinement phase B).
+template <int NMAX, int G, int SPIN, bool MSE, bool FP32>
 __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp64(PlanDev P, const double *__restrict__ map,
                                                   const double *__restrict__ theta,
                                                   const double *__restrict__ phi, int64_t n,
@@ -659,29 +799,30 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp64(PlanDev P, const do
     }
     const bool gact = (act_mask >> grp) & 1u;
     const bool ract = gact && row < nrow;
-    double *mat = B.mat + grp * L.matsz;
     int rowv = row;
     __asm__ volatile("" : "+v"(rowv));   // keeps row-dependent LDS addresses out of LICM
-    double a[NMAX];
-    double r[NR];
-    load_rows<NMAX, NR>(mat, B.rhs + grp * nrow * NR, rowv, ract, nrow, a, r);
-    double diag;
-    const bool ok = chol_rows<NMAX, G, NR>(a, r, rowv, grp, nug, diag);
-    double v0, v1, qd0, qd1, w0, w1;
-    epilogue<NMAX, G, SPIN, NR, MSE>(P, a, r, diag, gact, ract, row, mat, B.rbuf + grp * 4, v0, v1,
-                                    qd0, qd1, w0, w1);
+    GroupOut o;
+    bool ok;
+    if (FP32)
+      ok = fp32_phase_b<NMAX, G, SPIN, NR, MSE>(P, B.mat + grp * L.matsz, B.rhs + grp * nrow * NR,
+                                               rowv, grp, ract, nrow, nug, o);
+    else
+      ok = fp64_phase_b<NMAX, G, SPIN, NR, MSE>(B.mat + grp * L.matsz, B.rhs + grp * nrow * NR,
+                                               rowv, grp, ract, nrow, nug, o);
     if (row == 0) {
       const int64_t pt = g * PPW + grp;
-      if (pt < n) store_point<SPIN>(P, pt, n, gact, ok, v0, v1, qd0, qd1, w0, w1, nug, MSE, out, var);
+      if (pt < n)
+        store_point<SPIN>(P, pt, n, gact, ok, FP32 ? FAIL32_BITS : FAIL64_BITS, o, nug, MSE, out, var);
     }
   }
 }
 
-// Escalation pass (paper Sec. 2.4 nugget rule): every point tagged by the main
-// pass is recomputed alone, with n = mu + eps where mu is the smallest shift for
-// which S + mu I factorises (bisection on [n0, rows + 1]; the upper end is
-// positive definite by Gershgorin since |S_ij| <= 1).  Untagged chunks cost one
-// coalesced read of `out` per 64 points.
+// Fix-up pass over tagged points, one at a time.  A point rejected by the FP32
+// path is recomputed in FP64 (counted as an FP64 fallback); an FP64
+// factorisation failure gets the nugget of paper Sec. 2.4, n = mu + eps with mu
+// the smallest shift for which S + mu I factorises (bisection on [n0, rows + 1];
+// the upper end is positive definite by Gershgorin since |S_ij| <= 1).
+// Untagged chunks cost one coalesced read of `out` per 64 points.
 template <int NMAX, int G, int SPIN, bool MSE>
 __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate(PlanDev P, const double *__restrict__ map,
                                                   const double *__restrict__ theta,
@@ -703,43 +844,50 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate(PlanDev P, const do
   const int64_t nchunks = (n + WAVE - 1) / WAVE;
   for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb) {
     const int64_t p0 = ch * WAVE + lane;
-    const bool tagged = p0 < n && (unsigned long long)__double_as_longlong(out[p0]) == FAIL_BITS;
-    unsigned long long mask = __ballot(tagged);
+    const unsigned long long bits =
+        p0 < n ? (unsigned long long)__double_as_longlong(out[p0]) : 0ull;
+    const bool t64 = bits == FAIL64_BITS, t32 = bits == FAIL32_BITS;
+    unsigned long long mask = __ballot(t64 || t32);
+    const unsigned long long m32 = __ballot(t32);
     while (mask) {
       const int bit = __ffsll((long long)mask) - 1;
       mask &= mask - 1ull;
+      const bool from32 = (m32 >> bit) & 1ull;
       const int64_t pt = ch * WAVE + bit;
       const bool found = phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel);
       if (found)
         phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel, B.nb, B.mat, B.rhs);
       const bool gact = found && grp == 0;
       const bool ract = gact && row < nrow;
-      double a[NMAX];
-      double r[NR];
-      double diag;
-      double lo = nug0, hi = (double)nrow + 1.0;
-#pragma unroll 1
-      for (int it = 0; it < 64; ++it) {
-        const double mu = 0.5 * (lo + hi);
-        load_rows<NMAX, NR>(B.mat, B.rhs, row, ract, nrow, a, r);
-        const bool ok2 = __all(chol_rows<NMAX, G, NR>(a, r, row, grp, mu, diag) || !gact);
-        if (ok2) hi = mu; else lo = mu;
-      }
-      double nug = hi + P.eps;
+      GroupOut o;
+      double nug = nug0;
       bool ok = false;
+      if (from32) {
+        ok = __all(fp64_phase_b<NMAX, G, SPIN, NR, MSE>(B.mat, B.rhs, row, grp, ract, nrow, nug, o) || !gact);
+        if (lane == 0) atomicAdd(P.counters + CNT_FP64_FALLBACK, 1ull);
+      }
+      if (!ok) {
+        double lo = nug0, hi = (double)nrow + 1.0;
 #pragma unroll 1
-      for (int it = 0; it < 8 && !ok; ++it) {
-        load_rows<NMAX, NR>(B.mat, B.rhs, row, ract, nrow, a, r);
-        ok = __all(chol_rows<NMAX, G, NR>(a, r, row, grp, nug, diag) || !gact);
-        if (!ok) nug *= 2.0;
+        for (int it = 0; it < 64; ++it) {
+          const double mu = 0.5 * (lo + hi);
+          double a[NMAX];
+          double r[NR];
+          double diag;
+          load_rows<NMAX, NR>(B.mat, B.rhs, row, ract, nrow, a, r);
+          const bool ok2 = __all(chol_rows<NMAX, G, NR>(a, r, row, grp, mu, diag) || !gact);
+          if (ok2) hi = mu; else lo = mu;
+        }
+        nug = hi + P.eps;
+#pragma unroll 1
+        for (int it = 0; it < 8 && !ok; ++it) {
+          ok = __all(fp64_phase_b<NMAX, G, SPIN, NR, MSE>(B.mat, B.rhs, row, grp, ract, nrow, nug, o) ||
+                     !gact);
+          if (!ok) nug *= 2.0;
+        }
+        if (lane == 0) atomicAdd(P.counters + CNT_NUGGET_ESC, 1ull);
       }
-      double v0, v1, qd0, qd1, w0, w1;
-      epilogue<NMAX, G, SPIN, NR, MSE>(P, a, r, diag, gact, ract, row, B.mat, B.rbuf, v0, v1, qd0,
-                                      qd1, w0, w1);
-      if (lane == 0) {
-        atomicAdd(P.counters + CNT_NUGGET_ESC, 1ull);
-        store_point<SPIN>(P, pt, n, gact, ok, v0, v1, qd0, qd1, w0, w1, nug, MSE, out, var);
-      }
+      if (lane == 0) store_point<SPIN>(P, pt, n, gact, ok, FAIL64_BITS, o, nug, MSE, out, var);
     }
   }
 }
@@ -790,7 +938,7 @@ static DevLimits device_limits() {
   return d;
 }
 
-template <int NMAX, int G, int SPIN, bool MSE>
+template <int NMAX, int G, int SPIN, bool MSE, bool FP32>
 static int launch_t(const Plan *p, const double *map, const double *theta, const double *phi,
                     int64_t n, double *out, double *var, hipStream_t s) {
   constexpr int PPW = WAVE / G;
@@ -798,7 +946,7 @@ static int launch_t(const Plan *p, const double *map, const double *theta, const
   const DevLimits lim = device_limits();
   const int nrow = p->d.n;
   Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, nrow, PPW, G, NR);
-  auto kern = k_interp64<NMAX, G, SPIN, MSE>;
+  auto kern = k_interp64<NMAX, G, SPIN, MSE, FP32>;
   // waves per block: the count that puts the most waves on a CU given the LDS
   // (table shared per block) and register limits; cached per configuration
   static std::mutex mu;
@@ -851,25 +999,33 @@ static int launch_t(const Plan *p, const double *map, const double *theta, const
   return FLINTS_OK;
 }
 
-template <int SPIN, bool MSE>
+template <int SPIN, bool MSE, bool FP32>
 static int launch_spin(const Plan *p, const double *map, const double *theta, const double *phi,
                        int64_t n, double *out, double *var, hipStream_t s) {
   const int nrow = p->d.n;
-  if (nrow <= 16) return launch_t<16, 16, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
-  if (nrow <= 32) return launch_t<32, 32, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
-  if (nrow <= 48) return launch_t<48, 64, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
-  return launch_t<64, 64, SPIN, MSE>(p, map, theta, phi, n, out, var, s);
+  if (nrow <= 16) return launch_t<16, 16, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
+  if (nrow <= 32) return launch_t<32, 32, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
+  if (nrow <= 48) return launch_t<48, 64, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
+  return launch_t<64, 64, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
+}
+
+template <int SPIN>
+static int launch_prec(const Plan *p, const double *map, const double *theta, const double *phi,
+                       int64_t n, double *out, double *var, hipStream_t s) {
+  const bool mse = (p->d.var_kind == FLINTS_VAR_MSE) && var != nullptr;
+  const bool f32 = p->d.precision == FLINTS_FP32_IR;
+  if (f32)
+    return mse ? launch_spin<SPIN, true, true>(p, map, theta, phi, n, out, var, s)
+               : launch_spin<SPIN, false, true>(p, map, theta, phi, n, out, var, s);
+  return mse ? launch_spin<SPIN, true, false>(p, map, theta, phi, n, out, var, s)
+             : launch_spin<SPIN, false, false>(p, map, theta, phi, n, out, var, s);
 }
 
 int launch_interpolate(const Plan *p, const double *map, const double *theta, const double *phi,
                        int64_t n, double *out, double *var, hipStream_t s) {
   if (n == 0) return FLINTS_OK;
-  const bool mse = (p->d.var_kind == FLINTS_VAR_MSE) && var != nullptr;
-  if (p->d.spin == 0)
-    return mse ? launch_spin<0, true>(p, map, theta, phi, n, out, var, s)
-               : launch_spin<0, false>(p, map, theta, phi, n, out, var, s);
-  return mse ? launch_spin<2, true>(p, map, theta, phi, n, out, var, s)
-             : launch_spin<2, false>(p, map, theta, phi, n, out, var, s);
+  if (p->d.spin == 0) return launch_prec<0>(p, map, theta, phi, n, out, var, s);
+  return launch_prec<2>(p, map, theta, phi, n, out, var, s);
 }
 
 int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_t n, int64_t *idx,
