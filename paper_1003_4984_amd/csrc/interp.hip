@@ -48,8 +48,8 @@ __device__ inline void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)"
 __device__ inline void compiler_fence() { __asm__ volatile("" ::: "memory"); }
 __host__ __device__ inline int tri(int r) { return r * (r + 1) / 2; }
 
-// sin and cos of x for |x| <= 2 pi (all angles here are half longitude
-// differences).  x is reduced by the nearest multiple k of pi/2 with pi/2 split
+// sin and cos of x for |x| <= 2 pi (colatitudes, disc radii and half
+// longitude differences).  x is reduced by the nearest multiple k of pi/2 with pi/2 split
 // into a double and its remainder (x - k*hi is exact for |k| <= 4), then sin and
 // cos of |r| <= pi/4 come from their Taylor series (truncation < 1e-19).
 __device__ inline void sincos_bounded(double x, double &s, double &c) {
@@ -127,8 +127,7 @@ static inline int al16(int x) { return (x + 15) & ~15; }
 // (one neighbour-record slot, the packed systems and right-hand sides of all
 // PPW points).  The search of every point of the group runs before any
 // assembly, so the two uses never overlap.
-static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int G, int NR) {
-  (void)G;
+static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int NR) {
   Layout L;
   L.tab_bytes = al16(ntab * nf * 8);
   int o = 0;
@@ -143,10 +142,10 @@ static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int G, int NR
   int a = u0;
   L.off_nb = a;    a = al16(a + (K + 1) * NBF * 8);
   L.matsz = n * (n + 1) / 2;
-  L.off_mat = a;   a = al16(a + ppw * L.matsz * 8);
-  L.off_rhs = a;   a = al16(a + ppw * n * NR * 8);
+  L.off_mat = a;   a = al16(a + nsys * L.matsz * 8);
+  L.off_rhs = a;   a = al16(a + nsys * n * NR * 8);
   L.off_col = a;
-  L.off_rbuf = a;  a = al16(a + ppw * 4 * 8);
+  L.off_rbuf = a;  a = al16(a + nsys * 4 * 8);
   L.wave_bytes = s > a ? s : a;
   return L;
 }
@@ -162,12 +161,16 @@ __device__ inline void count_event(unsigned long long *ctr, bool cond, int lane)
 __device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st, double phr,
                               double r, int lane, double *cu, int *ci, RingSpan *rs) {
   const int64_t N = P.nside;
-  const double sr = sin(0.5 * r);
+  double sr, chr;
+  sincos_bounded(0.5 * r, sr, chr);
   const double ur = 2.0 * sr * sr;  // 1 - cos r
-  const double cr = cos(r);
+  const double cr = 1.0 - 2.0 * sr * sr;
   const bool pn = (th - r) <= 0.0, ps = (th + r) >= PI_D;
-  const double zhi = pn ? 1.0 : cos(th - r);
-  const double zlo = ps ? -1.0 : cos(th + r);
+  double s1, c1, s2, c2;
+  sincos_bounded(th - r, s1, c1);
+  sincos_bounded(th + r, s2, c2);
+  const double zhi = pn ? 1.0 : c1;
+  const double zlo = ps ? -1.0 : c2;
   int i0 = (int)floor(ring_coord(N, zhi)) - 1;
   if (i0 < 1) i0 = 1;
   int i1 = (int)ceil(ring_coord(N, zlo)) + 1;
@@ -256,7 +259,8 @@ __device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st,
 // K nearest pixels of (th, ph), ascending (distance, index), into sel[0..K).
 __device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, double *cu, int *ci,
                            RingSpan *rs, int *sel) {
-  const double zt = cos(th), st = sin(th);
+  double zt, st;
+  sincos_bounded(th, st, zt);
   const double phr = ph - TWO_PI_D * floor(ph / TWO_PI_D);
   const int K = P.K;
   double r = P.r0, rlo = 0.0, rhi = 0.0;
@@ -303,7 +307,8 @@ __device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, dou
 template <int SPIN>
 __device__ void neighbour_records(const PlanDev &P, double th, double ph, int lane, const int *sel,
                                   double *nb, const double *__restrict__ map) {
-  const double zt = cos(th), st = sin(th);
+  double zt, st;
+  sincos_bounded(th, st, zt);
   const double phr = ph - TWO_PI_D * floor(ph / TWO_PI_D);
   const int K = P.K;
   for (int a = lane; a <= K; a += WAVE) {
@@ -453,8 +458,19 @@ __device__ __forceinline__ void chol_step(T (&a)[NMAX], T (&r)[NR], int row, int
   ok = ok && (d > T(0));
   const T rs = rsqrt_t(d);
   const T c = (row > K) ? a[K] * rs * rs : T(0);
+  // broadcasts issued four at a time, so the VALU write of each SGPR pair is
+  // separated from its first read by independent work (no hazard stalls)
+  constexpr int CH = 4;
 #pragma unroll
-  for (int j = K + 1; j < NMAX; ++j) a[j] = fma(-c, group_bcast<G>(a[j], K, grp), a[j]);
+  for (int j0 = K + 1; j0 < NMAX; j0 += CH) {
+    T s[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (j0 + u < NMAX) s[u] = group_bcast<G>(a[j0 + u], K, grp);
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      if (j0 + u < NMAX) a[j0 + u] = fma(-c, s[u], a[j0 + u]);
+  }
 #pragma unroll
   for (int q = 0; q < NR; ++q) r[q] = fma(-c, group_bcast<G>(r[q], K, grp), r[q]);
   const T piv = d * rs;
@@ -602,6 +618,134 @@ __device__ inline double group_max(double v) {
 struct GroupOut {
   double v0, v1, qd0, qd1, w0, w1;
 };
+
+// ---------------------------------------------------------------- phase B, n <= 32
+// One system per 16-lane row of the wave (four points per wave).  Lane x of a
+// row group holds the lower-triangular rows x + 16 t (t < NT) of its point, row
+// x + 16 t in a[t][0 .. 16 t + 15] with the column as register index, plus the
+// right-hand sides of those rows.  The right-looking elimination needs, at step
+// k, the pivot a_kk and column k (a_jk of every row j > k): both sit in one lane
+// of the same 16-lane row, so each value reaches the whole row group through a
+// DPP row broadcast (one VALU move per value, no scalar registers).  The pivot
+// row is never scaled: row i is updated with c_i = a_ik / a_kk times the raw
+// a_jk, and the right-hand sides likewise, so after the last step r_i = L_ii y_i.
+
+// Value of v held by lane K of this lane's 16-lane row.
+template <int K>
+__device__ __forceinline__ double rbcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xf, 0xf, false);  // row_newbcast:K
+}
+
+// Compile-time loop: f(integral_constant<int, i>) for i in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void cfor(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    cfor<B + 1, E>(f);
+  }
+}
+
+template <int NT, int NR>
+struct RowSys {
+  double a[NT][16 * NT];   // a[t][j] used for j < 16 (t + 1)
+  double r[NT][NR];
+};
+
+// Identity rows with zero right-hand sides (inactive points and padding rows
+// factorise trivially and leave the real rows untouched).
+template <int NT, int NR>
+__device__ __forceinline__ void rowsys_identity(RowSys<NT, NR> &S, int x) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int j = 0; j < 16 * (t + 1); ++j) S.a[t][j] = (j == x + 16 * t) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) S.r[t][q] = 0.0;
+  }
+}
+
+// Rows x + 16 t of the packed system (lower triangle, row-major) into registers,
+// with the nugget added on the diagonal.  Entries right of the diagonal are zero.
+template <int NT, int NR>
+__device__ __forceinline__ void rowsys_load(RowSys<NT, NR> &S, const double *mat, const double *rhs,
+                                            int x_in, int nrow, double nug) {
+  int x = x_in;
+  __asm__ volatile("" : "+v"(x));   // row-dependent LDS addresses stay out of LICM
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int i = x + 16 * t;
+    const bool real = i < nrow;
+    const int ic = real ? i : 0;
+#pragma unroll
+    for (int j = 0; j < 16 * (t + 1); ++j) {
+      const double v = mat[tri(ic) + (j < ic ? j : ic)];
+      S.a[t][j] = real ? (j < i ? v : (j == i ? v + nug : 0.0)) : (j == i ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) S.r[t][q] = real ? rhs[ic * NR + q] : 0.0;
+  }
+}
+
+template <int NT, int NR, int K>
+__device__ __forceinline__ void rowsys_step(RowSys<NT, NR> &S, double (&dg)[NT], int x, bool &ok) {
+  constexpr int TK = K / 16, XK = K % 16, N = 16 * NT;
+  const double d = rbcast<XK>(S.a[TK][K]);
+  ok = ok && (d > 0.0);
+  const double rs = rsqrt(d);
+  const double rs2 = rs * rs;
+  double c[NT];
+#pragma unroll
+  for (int t = TK; t < NT; ++t) c[t] = (x + 16 * t > K) ? S.a[t][K] * rs2 : 0.0;
+  cfor<K + 1, N>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    const double b = rbcast<j % 16>(S.a[j / 16][K]);
+#pragma unroll
+    for (int t = (j / 16 > TK ? j / 16 : TK); t < NT; ++t) S.a[t][j] = fma(-c[t], b, S.a[t][j]);
+  });
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const double b = rbcast<XK>(S.r[TK][q]);
+#pragma unroll
+    for (int t = TK; t < NT; ++t) S.r[t][q] = fma(-c[t], b, S.r[t][q]);
+  }
+  dg[TK] = (x == XK) ? d * rs : dg[TK];
+  if constexpr (K + 1 < N) rowsys_step<NT, NR, K + 1>(S, dg, x, ok);
+}
+
+// Factorise, then value = y . z and quad = y . y per point as in fp64_phase_b.
+// Results are valid in every lane of the row group; ok is uniform in the group.
+template <int NT, int SPIN, int NR>
+__device__ inline bool rowsys_phase_b(RowSys<NT, NR> &S, int x, int nrow, GroupOut &o) {
+  double dg[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) dg[t] = 1.0;
+  bool ok = true;
+  rowsys_step<NT, NR, 0>(S, dg, x, ok);
+  double v0 = 0.0, v1 = 0.0, q0 = 0.0, q1 = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double inv = (x + 16 * t < nrow) ? 1.0 / dg[t] : 0.0;
+    const double y0 = S.r[t][0] * inv, y1 = S.r[t][1] * inv;
+    if (SPIN == 0) {
+      v0 = fma(y0, y1, v0);
+      q0 = fma(y0, y0, q0);
+    } else {
+      const double y2 = S.r[t][NR - 1] * inv;
+      v0 = fma(y0, y2, v0);
+      v1 = fma(y1, y2, v1);
+      q0 = fma(y0, y0, q0);
+      q1 = fma(y1, y1, q1);
+    }
+  }
+  o.v0 = group_sum<16>(v0);
+  o.qd0 = group_sum<16>(q0);
+  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
+  if (SPIN != 0) {
+    o.v1 = group_sum<16>(v1);
+    o.qd1 = group_sum<16>(q1);
+  }
+  return ok;
+}
 
 // FP64 phase B: factorise S + nI with the right-hand sides carried, then
 // value = y.z and quad = y.y per point (y = L^-1 b, z = L^-1 data); with MSE
@@ -892,6 +1036,136 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate(PlanDev P, const do
   }
 }
 
+// Main pass for systems of n <= 32 rows: four points per wave, one per 16-lane
+// row group.  Every point of the group is searched first; then each is
+// assembled in the wave's single system buffer and loaded into the registers
+// of its row group before the next point reuses the buffer, and phase B runs
+// for all four at once.
+template <int NT, int SPIN>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs(PlanDev P, const double *__restrict__ map,
+                                                   const double *__restrict__ theta,
+                                                   const double *__restrict__ phi, int64_t n,
+                                                   double *__restrict__ out,
+                                                   double *__restrict__ var, Layout L) {
+  constexpr int PPW = 4;
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  const int nrow = P.n;
+  const int K = P.K;
+  const int64_t ngroups = (n + PPW - 1) / PPW;
+  const int grp = lane >> 4;
+  const int x = lane & 15;
+  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+
+  for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb) {
+    unsigned act_mask = 0;
+#pragma unroll 1
+    for (int q = 0; q < PPW; ++q) {
+      const int64_t pt = g * PPW + q;
+      if (pt >= n) break;
+      if (phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K))
+        act_mask |= 1u << q;
+    }
+    RowSys<NT, NR> S;
+    rowsys_identity(S, x);
+#pragma unroll 1
+    for (int q = 0; q < PPW; ++q) {
+      if (!((act_mask >> q) & 1u)) continue;
+      const int64_t pt = g * PPW + q;
+      phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel + q * K, B.nb, B.mat,
+                              B.rhs);
+      if (grp == q) rowsys_load(S, B.mat, B.rhs, x, nrow, nug);
+    }
+    GroupOut o;
+    const bool ok = rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, o);
+    if (x == 0) {
+      const int64_t pt = g * PPW + grp;
+      if (pt < n)
+        store_point<SPIN>(P, pt, n, (act_mask >> grp) & 1u, ok, FAIL64_BITS, o, nug, false, out, var);
+    }
+  }
+}
+
+// Fix-up pass of the n <= 32 path (same policy as k_escalate): the point is
+// carried by row group 0, so an FP32-rejected point is recomputed with exactly
+// the arithmetic of k_interp_rs.
+template <int NT, int SPIN>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate_rs(PlanDev P, const double *__restrict__ map,
+                                                     const double *__restrict__ theta,
+                                                     const double *__restrict__ phi, int64_t n,
+                                                     double *__restrict__ out,
+                                                     double *__restrict__ var, Layout L) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  const int nrow = P.n;
+  const int grp = lane >> 4;
+  const int x = lane & 15;
+  const double nug0 = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+  const int64_t nchunks = (n + WAVE - 1) / WAVE;
+  for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb) {
+    const int64_t p0 = ch * WAVE + lane;
+    const unsigned long long bits =
+        p0 < n ? (unsigned long long)__double_as_longlong(out[p0]) : 0ull;
+    const bool t64 = bits == FAIL64_BITS, t32 = bits == FAIL32_BITS;
+    unsigned long long mask = __ballot(t64 || t32);
+    const unsigned long long m32 = __ballot(t32);
+    while (mask) {
+      const int bit = __ffsll((long long)mask) - 1;
+      mask &= mask - 1ull;
+      const bool from32 = (m32 >> bit) & 1ull;
+      const int64_t pt = ch * WAVE + bit;
+      const bool found = phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel);
+      if (found)
+        phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel, B.nb, B.mat, B.rhs);
+      const bool gact = found && grp == 0;
+      GroupOut o;
+      double nug = nug0;
+      bool ok = false;
+      RowSys<NT, NR> S;
+      if (from32) {
+        rowsys_identity(S, x);
+        if (gact) rowsys_load(S, B.mat, B.rhs, x, nrow, nug);
+        ok = __all(rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, o));
+        if (lane == 0) atomicAdd(P.counters + CNT_FP64_FALLBACK, 1ull);
+      }
+      if (!ok) {
+        double lo = nug0, hi = (double)nrow + 1.0;
+#pragma unroll 1
+        for (int it = 0; it < 64; ++it) {
+          const double mu = 0.5 * (lo + hi);
+          rowsys_identity(S, x);
+          if (gact) rowsys_load(S, B.mat, B.rhs, x, nrow, mu);
+          GroupOut tmp;
+          const bool ok2 = __all(rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, tmp));
+          if (ok2) hi = mu; else lo = mu;
+        }
+        nug = hi + P.eps;
+#pragma unroll 1
+        for (int it = 0; it < 8 && !ok; ++it) {
+          rowsys_identity(S, x);
+          if (gact) rowsys_load(S, B.mat, B.rhs, x, nrow, nug);
+          ok = __all(rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, o));
+          if (!ok) nug *= 2.0;
+        }
+        if (lane == 0) atomicAdd(P.counters + CNT_NUGGET_ESC, 1ull);
+      }
+      if (lane == 0) store_point<SPIN>(P, pt, n, gact, ok, FAIL64_BITS, o, nug, false, out, var);
+    }
+  }
+}
+
 // Stencil only (a2/a3): K nearest pixel indices per target.
 __global__ __launch_bounds__(STENCIL_WPB * WAVE) void k_stencil(PlanDev P, const double *__restrict__ theta,
                                                  const double *__restrict__ phi, int64_t n,
@@ -938,25 +1212,22 @@ static DevLimits device_limits() {
   return d;
 }
 
-template <int NMAX, int G, int SPIN, bool MSE, bool FP32>
-static int launch_t(const Plan *p, const double *map, const double *theta, const double *phi,
-                    int64_t n, double *out, double *var, hipStream_t s) {
-  constexpr int PPW = WAVE / G;
-  constexpr int NR = (SPIN == 0) ? 2 : 3;
+// Launches the main pass and the fix-up pass over the same LDS layout.  Waves
+// per block: the count that puts the most waves on a CU given the LDS (table
+// shared per block) and the kernel's register use; cached per kernel and layout.
+template <typename KM, typename KE>
+static int launch_pair(KM kern, KE esc, const Plan *p, const Layout &L, int ppw, const double *map,
+                       const double *theta, const double *phi, int64_t n, double *out, double *var,
+                       hipStream_t s) {
   const DevLimits lim = device_limits();
-  const int nrow = p->d.n;
-  Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, nrow, PPW, G, NR);
-  auto kern = k_interp64<NMAX, G, SPIN, MSE, FP32>;
-  // waves per block: the count that puts the most waves on a CU given the LDS
-  // (table shared per block) and register limits; cached per configuration
   static std::mutex mu;
-  static std::map<std::tuple<int, int, int>, std::pair<int, int>> cache;
+  static std::map<std::tuple<int, const void *, int, int>, std::pair<int, int>> cache;
   int wpb = 0, occ = 0;
   {
     std::lock_guard<std::mutex> g(mu);
     int dev = 0;
     hipGetDevice(&dev);
-    const auto key = std::make_tuple(dev, L.tab_bytes, L.wave_bytes);
+    const auto key = std::make_tuple(dev, (const void *)kern, L.tab_bytes, L.wave_bytes);
     auto it = cache.find(key);
     if (it != cache.end()) {
       wpb = it->second.first;
@@ -981,12 +1252,11 @@ static int launch_t(const Plan *p, const double *map, const double *theta, const
   const int lds = L.tab_bytes + wpb * L.wave_bytes;
   hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (occ < 1) occ = 1;
-  const int64_t ngroups = (n + PPW - 1) / PPW;
+  const int64_t ngroups = (n + ppw - 1) / ppw;
   int64_t blocks = std::min<int64_t>((ngroups + wpb - 1) / wpb, (int64_t)lim.ncu * occ);
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(wpb * WAVE), lds, s, p->d, map, theta,
                      phi, n, out, var, L);
-  auto esc = k_escalate<NMAX, G, SPIN, MSE>;
   hipFuncSetAttribute((const void *)esc, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   const int64_t eblocks = std::min<int64_t>(((n + WAVE - 1) / WAVE + wpb - 1) / wpb, (int64_t)lim.ncu * 4);
   hipLaunchKernelGGL(esc, dim3((unsigned)std::max<int64_t>(eblocks, 1)), dim3(wpb * WAVE), lds, s, p->d,
@@ -999,10 +1269,40 @@ static int launch_t(const Plan *p, const double *map, const double *theta, const
   return FLINTS_OK;
 }
 
+// Register-row path (one row per lane, groups of G lanes).
+template <int NMAX, int G, int SPIN, bool MSE, bool FP32>
+static int launch_t(const Plan *p, const double *map, const double *theta, const double *phi,
+                    int64_t n, double *out, double *var, hipStream_t s) {
+  constexpr int PPW = WAVE / G;
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, PPW, PPW, NR);
+  return launch_pair(k_interp64<NMAX, G, SPIN, MSE, FP32>, k_escalate<NMAX, G, SPIN, MSE>, p, L, PPW,
+                     map, theta, phi, n, out, var, s);
+}
+
+// Row-group path for n <= 16 NT (FP64), and the FP32 main pass of the same
+// sizes whose rejected points are recomputed by the row-group fix-up.
+template <int NT, int SPIN, bool FP32>
+static int launch_rs(const Plan *p, const double *map, const double *theta, const double *phi,
+                     int64_t n, double *out, double *var, hipStream_t s) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  if (FP32) {
+    constexpr int G = 16 * NT, PPW = WAVE / G;
+    const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, PPW, PPW, NR);
+    return launch_pair(k_interp64<16 * NT, G, SPIN, false, true>, k_escalate_rs<NT, SPIN>, p, L, PPW,
+                       map, theta, phi, n, out, var, s);
+  }
+  const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 4, 1, NR);
+  return launch_pair(k_interp_rs<NT, SPIN>, k_escalate_rs<NT, SPIN>, p, L, 4, map, theta, phi, n,
+                     out, var, s);
+}
+
 template <int SPIN, bool MSE, bool FP32>
 static int launch_spin(const Plan *p, const double *map, const double *theta, const double *phi,
                        int64_t n, double *out, double *var, hipStream_t s) {
   const int nrow = p->d.n;
+  if (!MSE && nrow <= 16) return launch_rs<1, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
+  if (!MSE && nrow <= 32) return launch_rs<2, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
   if (nrow <= 16) return launch_t<16, 16, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
   if (nrow <= 32) return launch_t<32, 32, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
   if (nrow <= 48) return launch_t<48, 64, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
@@ -1032,7 +1332,7 @@ int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_
                    hipStream_t s) {
   if (n == 0) return FLINTS_OK;
   const DevLimits lim = device_limits();
-  Layout L = make_layout(0, 1, p->d.K, 1, 1, 64, 2);
+  Layout L = make_layout(0, 1, p->d.K, 1, 1, 1, 2);
   const int wpb = STENCIL_WPB;
   const int lds = wpb * L.wave_bytes;
   hipFuncSetAttribute((const void *)k_stencil, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
