@@ -127,7 +127,7 @@ static inline int al16(int x) { return (x + 15) & ~15; }
 // (one neighbour-record slot, the packed systems and right-hand sides of all
 // PPW points).  The search of every point of the group runs before any
 // assembly, so the two uses never overlap.
-static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int NR) {
+static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int NR, int min_mat = 0) {
   Layout L;
   L.tab_bytes = al16(ntab * nf * 8);
   int o = 0;
@@ -141,7 +141,7 @@ static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int
   // assembly view
   int a = u0;
   L.off_nb = a;    a = al16(a + (K + 1) * NBF * 8);
-  L.matsz = n * (n + 1) / 2;
+  L.matsz = std::max(n * (n + 1) / 2, min_mat);
   L.off_mat = a;   a = al16(a + nsys * L.matsz * 8);
   L.off_rhs = a;   a = al16(a + nsys * n * NR * 8);
   L.off_col = a;
@@ -747,6 +747,179 @@ __device__ inline bool rowsys_phase_b(RowSys<NT, NR> &S, int x, int nrow, GroupO
   return ok;
 }
 
+// ---------------------------------------------------------------- phase B, 32 < n <= 64
+// Blocked right-looking Cholesky of one system per wave on 16 x 16 tiles.  For
+// block column J the wave's four 16-lane row groups each take one block row
+// J + rho (rho = 0 .. 3): every group holds a replica of the diagonal tile (row x
+// of it in lane x) and its own panel tile, and eliminates the 16 columns with
+// DPP row broadcasts as in the row-group path, which factors the diagonal tile
+// and solves the panel L_rJ = A_rJ L_JJ^-T at once.  The trailing tiles then
+// take A_rs -= L_rJ L_sJ^T on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
+// with the panels staged through LDS into the MFMA operand layout.  Trailing
+// tiles live in registers in the MFMA accumulator layout: lane l, element v
+// holds tile entry (4 v + l / 16, l % 16).  The right-hand sides ride along in
+// the elimination and return to LDS between block columns.
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int TSTR = 18;             // row stride (doubles) of a staged 16 x 16 tile
+constexpr int TILE_D = 16 * TSTR;    // doubles per staged tile
+
+template <int T>
+struct TileSys {
+  dbl4 c[T][T];   // c[r][s], 1 <= s <= r < T
+};
+
+// S + nI entry (i, j) of the packed system, identity beyond n.
+__device__ __forceinline__ double packed_entry(const double *mat, int i, int j, int nrow, double nug) {
+  const bool real = (i < nrow) && (j < nrow);
+  const int hi = i > j ? i : j, lo = i > j ? j : i;
+  const double v = mat[real ? tri(hi) + lo : 0];
+  return real ? (i == j ? v + nug : v) : (i == j ? 1.0 : 0.0);
+}
+
+template <int T>
+__device__ __forceinline__ void tiles_load(TileSys<T> &S, const double *mat, int l, int nrow, double nug) {
+#pragma unroll
+  for (int r = 1; r < T; ++r)
+#pragma unroll
+    for (int s = 1; s <= r; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        S.c[r][s][v] = packed_entry(mat, 16 * r + 4 * v + (l >> 4), 16 * s + (l & 15), nrow, nug);
+}
+
+struct TileAcc {
+  double v0, v1, q0, q1;
+};
+
+template <int T, int SPIN, int NR, int J>
+__device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rhs, const double *mat,
+                                          int l, int nrow, double nug, TileAcc &acc, bool &ok) {
+  const int rho = l >> 4, x = l & 15;
+  const int rp = J + rho;                       // block row of this row group
+  const bool prow = (rho > 0) && (rp < T);      // group carries a panel tile
+  double d[16], p[16], dr[NR], pr[NR];
+  if constexpr (J == 0) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      d[j] = packed_entry(mat, x, j, nrow, nug);
+      p[j] = prow ? packed_entry(mat, 16 * rp + x, j, nrow, nug) : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int r = J; r < T; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) scr[(r - J) * TILE_D + (4 * v + rho) * TSTR + x] = S.c[r][J][v];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      d[j] = scr[x * TSTR + j];
+      p[j] = prow ? scr[rho * TILE_D + x * TSTR + j] : 0.0;
+    }
+  }
+  const int ir = 16 * J + x, ip = 16 * rp + x;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    dr[q] = (ir < nrow) ? rhs[ir * NR + q] : 0.0;
+    pr[q] = (prow && ip < nrow) ? rhs[ip * NR + q] : 0.0;
+  }
+  double dg = 1.0;
+  cfor<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const double piv2 = rbcast<k>(d[k]);
+    ok = ok && (piv2 > 0.0);
+    const double rs = rsqrt(piv2);
+    const double rs2 = rs * rs;
+    const double cd = (x > k) ? d[k] * rs2 : 0.0;
+    const double cp = p[k] * rs2;
+    cfor<k + 1, 16>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const double b = rbcast<k>(d[j]);
+      d[j] = fma(-cd, b, d[j]);
+      if constexpr (J + 1 < T) p[j] = fma(-cp, b, p[j]);
+    });
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const double b = rbcast<k>(dr[q]);
+      dr[q] = fma(-cd, b, dr[q]);
+      if constexpr (J + 1 < T) pr[q] = fma(-cp, b, pr[q]);
+    }
+    dg = (x == k) ? piv2 * rs : dg;
+    p[k] = p[k] * rs;
+  });
+  if constexpr (J + 1 < T) {
+    // the panel is consumed only under `prow`; pin it here so its elimination is
+    // not sunk into that branch (which would keep every broadcast value live)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) __asm__ volatile("" ::"v"(p[j]));
+#pragma unroll
+    for (int q = 0; q < NR; ++q) __asm__ volatile("" ::"v"(pr[q]));
+  }
+  // rows of block J are final: y = r / L_ii (counted once, by row group 0)
+  if (rho == 0 && ir < nrow) {
+    const double inv = 1.0 / dg;
+    const double y0 = dr[0] * inv, y1 = dr[1] * inv;
+    if (SPIN == 0) {
+      acc.v0 = fma(y0, y1, acc.v0);
+      acc.q0 = fma(y0, y0, acc.q0);
+    } else {
+      const double y2 = dr[NR - 1] * inv;
+      acc.v0 = fma(y0, y2, acc.v0);
+      acc.v1 = fma(y1, y2, acc.v1);
+      acc.q0 = fma(y0, y0, acc.q0);
+      acc.q1 = fma(y1, y1, acc.q1);
+    }
+  }
+  if constexpr (J + 1 < T) {
+    if (prow && ip < nrow) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) rhs[ip * NR + q] = pr[q];
+    }
+    // panels L_rJ (r > J) to LDS, then into the MFMA operand layout:
+    // fr[r][m] at lane l = L_rJ(l % 16, 4 m + l / 16)
+    if (prow) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) scr[(rho - 1) * TILE_D + x * TSTR + j] = p[j];
+    }
+    double fr[T][4];
+#pragma unroll
+    for (int r = J + 1; r < T; ++r)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) fr[r][m] = scr[(r - J - 1) * TILE_D + x * TSTR + 4 * m + rho];
+#pragma unroll
+    for (int r = J + 1; r < T; ++r)
+#pragma unroll
+      for (int s = J + 1; s <= r; ++s)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          S.c[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fr[r][m], fr[s][m], S.c[r][s], 0, 0, 0);
+    tile_step<T, SPIN, NR, J + 1>(S, scr, rhs, mat, l, nrow, nug, acc, ok);
+  }
+}
+
+// Factorise the wave's system (packed in mat, right-hand sides in rhs) and
+// return value / quad sums as fp64_phase_b does.  scr may overlay mat (mat is
+// read in full before the first staged tile is written); rhs is overwritten.
+template <int T, int SPIN, int NR>
+__device__ inline bool tile_phase_b(const double *mat, double *rhs, double *scr, int lane_in, int nrow,
+                                    double nug, GroupOut &o) {
+  int l = lane_in;
+  __asm__ volatile("" : "+v"(l));   // lane-dependent LDS addresses stay out of LICM
+  TileSys<T> S;
+  tiles_load<T>(S, mat, l, nrow, nug);
+  TileAcc acc{0.0, 0.0, 0.0, 0.0};
+  bool ok = true;
+  tile_step<T, SPIN, NR, 0>(S, scr, rhs, mat, l, nrow, nug, acc, ok);
+  o.v0 = group_sum<WAVE>(acc.v0);
+  o.qd0 = group_sum<WAVE>(acc.q0);
+  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
+  if (SPIN != 0) {
+    o.v1 = group_sum<WAVE>(acc.v1);
+    o.qd1 = group_sum<WAVE>(acc.q1);
+  }
+  return ok;
+}
+
 // FP64 phase B: factorise S + nI with the right-hand sides carried, then
 // value = y.z and quad = y.y per point (y = L^-1 b, z = L^-1 data); with MSE
 // also |w|^2 for w = L^-T y (register-local backward solve).
@@ -1092,15 +1265,41 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs(PlanDev P, const d
   }
 }
 
-// Fix-up pass of the n <= 32 path (same policy as k_escalate): the point is
-// carried by row group 0, so an FP32-rejected point is recomputed with exactly
-// the arithmetic of k_interp_rs.
+// Phase-B engines of the fix-up pass: solve the tagged point (searched and
+// assembled into the wave's first system buffer) with nugget nug, using
+// exactly the arithmetic of the matching main pass.  `first` is false when an
+// earlier attempt may have overwritten the assembled system.
 template <int NT, int SPIN>
-__global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate_rs(PlanDev P, const double *__restrict__ map,
-                                                     const double *__restrict__ theta,
-                                                     const double *__restrict__ phi, int64_t n,
-                                                     double *__restrict__ out,
-                                                     double *__restrict__ var, Layout L) {
+struct RowGroupEngine {
+  static constexpr int NR = (SPIN == 0) ? 2 : 3;
+  __device__ static bool solve(const PlanDev &P, const double *, const double *, double, double, int lane,
+                               const WaveBufs &B, bool found, bool, double nug, GroupOut &o) {
+    RowSys<NT, NR> S;
+    rowsys_identity(S, lane & 15);
+    if (found && (lane >> 4) == 0) rowsys_load(S, B.mat, B.rhs, lane & 15, P.n, nug);
+    return __all(rowsys_phase_b<NT, SPIN, NR>(S, lane & 15, P.n, o));
+  }
+};
+
+template <int T, int SPIN>
+struct TileEngine {
+  static constexpr int NR = (SPIN == 0) ? 2 : 3;
+  __device__ static bool solve(const PlanDev &P, const double *tab, const double *map, double th,
+                               double ph, int lane, const WaveBufs &B, bool found, bool first,
+                               double nug, GroupOut &o) {
+    if (!found) return true;
+    if (!first) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
+    return __all(tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o));
+  }
+};
+
+// Fix-up pass of the row-group and tile paths (same policy as k_escalate).
+template <class Eng, int SPIN>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_fixup(PlanDev P, const double *__restrict__ map,
+                                               const double *__restrict__ theta,
+                                               const double *__restrict__ phi, int64_t n,
+                                               double *__restrict__ out,
+                                               double *__restrict__ var, Layout L) {
   constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
@@ -1110,8 +1309,6 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate_rs(PlanDev P, const
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
   const int nrow = P.n;
-  const int grp = lane >> 4;
-  const int x = lane & 15;
   const double nug0 = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
   const int64_t nchunks = (n + WAVE - 1) / WAVE;
   for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb) {
@@ -1126,18 +1323,15 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate_rs(PlanDev P, const
       mask &= mask - 1ull;
       const bool from32 = (m32 >> bit) & 1ull;
       const int64_t pt = ch * WAVE + bit;
-      const bool found = phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel);
-      if (found)
-        phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel, B.nb, B.mat, B.rhs);
-      const bool gact = found && grp == 0;
+      const double th = theta[pt], ph = phi[pt];
+      const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
+      if (found) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
       GroupOut o;
       double nug = nug0;
-      bool ok = false;
-      RowSys<NT, NR> S;
+      bool ok = false, first = true;
       if (from32) {
-        rowsys_identity(S, x);
-        if (gact) rowsys_load(S, B.mat, B.rhs, x, nrow, nug);
-        ok = __all(rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, o));
+        ok = Eng::solve(P, tab, map, th, ph, lane, B, found, first, nug, o);
+        first = false;
         if (lane == 0) atomicAdd(P.counters + CNT_FP64_FALLBACK, 1ull);
       }
       if (!ok) {
@@ -1145,24 +1339,51 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate_rs(PlanDev P, const
 #pragma unroll 1
         for (int it = 0; it < 64; ++it) {
           const double mu = 0.5 * (lo + hi);
-          rowsys_identity(S, x);
-          if (gact) rowsys_load(S, B.mat, B.rhs, x, nrow, mu);
           GroupOut tmp;
-          const bool ok2 = __all(rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, tmp));
+          const bool ok2 = Eng::solve(P, tab, map, th, ph, lane, B, found, first, mu, tmp);
+          first = false;
           if (ok2) hi = mu; else lo = mu;
         }
         nug = hi + P.eps;
 #pragma unroll 1
         for (int it = 0; it < 8 && !ok; ++it) {
-          rowsys_identity(S, x);
-          if (gact) rowsys_load(S, B.mat, B.rhs, x, nrow, nug);
-          ok = __all(rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, o));
+          ok = Eng::solve(P, tab, map, th, ph, lane, B, found, false, nug, o);
           if (!ok) nug *= 2.0;
         }
         if (lane == 0) atomicAdd(P.counters + CNT_NUGGET_ESC, 1ull);
       }
-      if (lane == 0) store_point<SPIN>(P, pt, n, gact, ok, FAIL64_BITS, o, nug, false, out, var);
+      if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
     }
+  }
+}
+
+// Main pass for 32 < n <= 16 T: one point per wave, blocked tile Cholesky.
+template <int T, int SPIN>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const double *__restrict__ map,
+                                                     const double *__restrict__ theta,
+                                                     const double *__restrict__ phi, int64_t n,
+                                                     double *__restrict__ out,
+                                                     double *__restrict__ var, Layout L) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  const int nrow = P.n;
+  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+  for (int64_t pt = (int64_t)blockIdx.x * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb) {
+    const double th = theta[pt], ph = phi[pt];
+    const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
+    GroupOut o;
+    bool ok = true;
+    if (found) {
+      phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
+      ok = tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, nrow, nug, o);
+    }
+    if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
   }
 }
 
@@ -1289,12 +1510,30 @@ static int launch_rs(const Plan *p, const double *map, const double *theta, cons
   if (FP32) {
     constexpr int G = 16 * NT, PPW = WAVE / G;
     const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, PPW, PPW, NR);
-    return launch_pair(k_interp64<16 * NT, G, SPIN, false, true>, k_escalate_rs<NT, SPIN>, p, L, PPW,
-                       map, theta, phi, n, out, var, s);
+    return launch_pair(k_interp64<16 * NT, G, SPIN, false, true>, k_fixup<RowGroupEngine<NT, SPIN>, SPIN>,
+                       p, L, PPW, map, theta, phi, n, out, var, s);
   }
   const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 4, 1, NR);
-  return launch_pair(k_interp_rs<NT, SPIN>, k_escalate_rs<NT, SPIN>, p, L, 4, map, theta, phi, n,
-                     out, var, s);
+  return launch_pair(k_interp_rs<NT, SPIN>, k_fixup<RowGroupEngine<NT, SPIN>, SPIN>, p, L, 4, map,
+                     theta, phi, n, out, var, s);
+}
+
+// Tile path for 16 (T - 1) < n <= 16 T (FP64), and the FP32 main pass of the
+// same sizes whose rejected points are recomputed by the tile fix-up.
+template <int T, int SPIN, bool FP32>
+static int launch_tile(const Plan *p, const double *map, const double *theta, const double *phi,
+                       int64_t n, double *out, double *var, hipStream_t s) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  constexpr int SCR = (T - 1) * TILE_D;   // staged tiles overlay the packed system
+  if (FP32) {
+    constexpr int G = 64, PPW = 1;
+    const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, PPW, PPW, NR, SCR);
+    return launch_pair(k_interp64<16 * T, G, SPIN, false, true>, k_fixup<TileEngine<T, SPIN>, SPIN>, p,
+                       L, PPW, map, theta, phi, n, out, var, s);
+  }
+  const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 1, 1, NR, SCR);
+  return launch_pair(k_interp_tile<T, SPIN>, k_fixup<TileEngine<T, SPIN>, SPIN>, p, L, 1, map, theta,
+                     phi, n, out, var, s);
 }
 
 template <int SPIN, bool MSE, bool FP32>
@@ -1303,6 +1542,8 @@ static int launch_spin(const Plan *p, const double *map, const double *theta, co
   const int nrow = p->d.n;
   if (!MSE && nrow <= 16) return launch_rs<1, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
   if (!MSE && nrow <= 32) return launch_rs<2, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
+  if (!MSE && nrow <= 48) return launch_tile<3, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
+  if (!MSE) return launch_tile<4, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
   if (nrow <= 16) return launch_t<16, 16, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
   if (nrow <= 32) return launch_t<32, 32, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);
   if (nrow <= 48) return launch_t<48, 64, SPIN, MSE, FP32>(p, map, theta, phi, n, out, var, s);

@@ -56,11 +56,12 @@ def test_fp32ir_parity_spin2(gpu_ok, mode):
     compare(v, var, vo, varo, 2e-4, 1e-2, 1e-9 * p.info()["sigma2"])
 
 
-@pytest.mark.parametrize("spin", [0, 2])
-def test_forced_fallback_equals_fp64(gpu_ok, spin):
+@pytest.mark.parametrize("spin,K", [(0, 16), (2, 16), (0, 40), (2, 32)])
+def test_forced_fallback_equals_fp64(gpu_ok, spin, K):
     """Pivot-ratio threshold 1 rejects every FP32 factorisation; the FP64
-    recompute must then reproduce the FP64 path bit for bit."""
-    nside, lmax, K = 32, 80, 16
+    recompute must then reproduce the FP64 path bit for bit (row-group sizes
+    n <= 32 and tile sizes n > 32)."""
+    nside, lmax = 32, 80
     tt, ee, te, bb = spectra.cl_acoustic(lmax)
     rng = seeds.rng(8, spin, 0)
     if spin == 0:
