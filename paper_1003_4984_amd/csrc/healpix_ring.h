@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <math.h>
+#include "kconst.h"
 
 namespace flints {
 
@@ -22,20 +23,20 @@ struct Ring {
 // Ring i (1-based, 1 <= i <= 4N-1).
 __host__ __device__ inline Ring ring_geom(int64_t N, int32_t i) {
   Ring r;
-  const double PI = 3.14159265358979323846;
+  const double TWO_PI = kconst(6.28318530717958647692);
   if (i < N) {
     double omz = (double)i * (double)i / (3.0 * (double)N * (double)N);
     r.z = 1.0 - omz;
     r.s = sqrt(omz * (2.0 - omz));
     r.n = 4 * i;
-    r.dphi = 2.0 * PI / (double)r.n;
+    r.dphi = TWO_PI / (double)r.n;
     r.phi0 = 0.5 * r.dphi;
     r.first = 2 * (int64_t)i * (int64_t)(i - 1);
   } else if (i <= 3 * N) {
     r.z = 2.0 * (double)(2 * N - i) / (3.0 * (double)N);
     r.s = sqrt((1.0 - r.z) * (1.0 + r.z));
     r.n = (int32_t)(4 * N);
-    r.dphi = 2.0 * PI / (double)r.n;
+    r.dphi = TWO_PI / (double)r.n;
     r.phi0 = (((i - N) & 1) == 0) ? 0.5 * r.dphi : 0.0;
     r.first = 2 * N * (N - 1) + 4 * N * (int64_t)(i - N);
   } else {
@@ -44,7 +45,7 @@ __host__ __device__ inline Ring ring_geom(int64_t N, int32_t i) {
     r.z = -(1.0 - omz);
     r.s = sqrt(omz * (2.0 - omz));
     r.n = 4 * k;
-    r.dphi = 2.0 * PI / (double)r.n;
+    r.dphi = TWO_PI / (double)r.n;
     r.phi0 = 0.5 * r.dphi;
     r.first = 12 * N * N - 2 * (int64_t)k * (int64_t)(k + 1);
   }
@@ -70,7 +71,7 @@ __host__ __device__ inline int32_t pix_ring(int64_t N, int64_t p) {
 
 // Continuous ring coordinate of colatitude cosine z (ring i sits at i exactly).
 __host__ __device__ inline double ring_coord(int64_t N, double z) {
-  const double twothird = 2.0 / 3.0;
+  const double twothird = kconst(2.0 / 3.0);
   if (z >= twothird) return (double)N * sqrt(3.0 * (1.0 - z));
   if (z <= -twothird) return 4.0 * (double)N - (double)N * sqrt(3.0 * (1.0 + z));
   return (double)N * (2.0 - 1.5 * z);

@@ -27,6 +27,7 @@
 #include "plan.h"
 #include "healpix_ring.h"
 #include "table_interp.h"
+#include "kconst.h"
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -49,34 +50,30 @@ __device__ inline void compiler_fence() { __asm__ volatile("" ::: "memory"); }
 __host__ __device__ inline int tri(int r) { return r * (r + 1) / 2; }
 
 // sin and cos of x for |x| <= 2 pi (colatitudes, disc radii and half
-// longitude differences).  x is reduced by the nearest multiple k of pi/2 with pi/2 split
-// into a double and its remainder (x - k*hi is exact for |k| <= 4), then sin and
-// cos of |r| <= pi/4 come from their Taylor series (truncation < 1e-19).
+// longitude differences).  x is reduced by the nearest multiple k of pi/2 with
+// pi/2 split into a double and its remainder (x - k*hi is exact for |k| <= 4),
+// then sin and cos of |r| <= pi/4 come from their Taylor series (truncation
+// < 1e-19).
 __device__ inline void sincos_bounded(double x, double &s, double &c) {
-  const double PIO2_HI = 1.5707963267948966;      // pi/2 rounded to double
-  const double PIO2_LO = 6.123233995736766e-17;   // pi/2 - PIO2_HI
-  const double k = rint(x * 0.6366197723675814);
-  const double r = fma(-k, PIO2_LO, fma(-k, PIO2_HI, x));
+  constexpr double PIO2_HI = 1.5707963267948966;      // pi/2 rounded to double
+  constexpr double PIO2_LO = 6.123233995736766e-17;   // pi/2 - PIO2_HI
+  constexpr double TWO_OVER_PI = 0.6366197723675814;
+  // sin r = r - r^3 (1/3! - r^2/5! + ... + r^14/17!), coefficients 1/(2i+1)! with signs
+  constexpr double SC[8] = {-1.0 / 355687428096000.0, 1.0 / 1307674368000.0, -1.0 / 6227020800.0,
+                            1.0 / 39916800.0, -1.0 / 362880.0, 1.0 / 5040.0, -1.0 / 120.0, 1.0 / 6.0};
+  // cos r = 1 + r^2 (-1/2! + r^2/4! - ... + r^14/16!)
+  constexpr double CC[8] = {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
+                            -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5};
+  const double k = rint(x * kconst(TWO_OVER_PI));
+  const double r = fma(-k, kconst(PIO2_LO), fma(-k, kconst(PIO2_HI), x));
   const double r2 = r * r;
-  // sin r = r (1 - r^2/3! + r^4/5! - ... - r^16/17!)
-  double ps = -1.0 / 355687428096000.0;            // -1/17!
-  ps = fma(ps, r2, 1.0 / 1307674368000.0);         // 1/15!
-  ps = fma(ps, r2, -1.0 / 6227020800.0);           // -1/13!
-  ps = fma(ps, r2, 1.0 / 39916800.0);              // 1/11!
-  ps = fma(ps, r2, -1.0 / 362880.0);               // -1/9!
-  ps = fma(ps, r2, 1.0 / 5040.0);                  // 1/7!
-  ps = fma(ps, r2, -1.0 / 120.0);                  // -1/5!... sign pattern continues
-  ps = fma(ps, r2, 1.0 / 6.0);
-  const double sr = fma(-r * r2, ps, r);           // r - r^3 (1/3! - r^2/5! + ...)
-  // cos r = 1 - r^2/2! + r^4/4! - ... + r^16/16!
-  double pc = 1.0 / 20922789888000.0;              // 1/16!
-  pc = fma(pc, r2, -1.0 / 87178291200.0);          // -1/14!
-  pc = fma(pc, r2, 1.0 / 479001600.0);             // 1/12!
-  pc = fma(pc, r2, -1.0 / 3628800.0);              // -1/10!
-  pc = fma(pc, r2, 1.0 / 40320.0);                 // 1/8!
-  pc = fma(pc, r2, -1.0 / 720.0);                  // -1/6!
-  pc = fma(pc, r2, 1.0 / 24.0);                    // 1/4!
-  pc = fma(pc, r2, -0.5);
+  double ps = kconst(SC[0]);
+#pragma unroll
+  for (int i = 1; i < 8; ++i) ps = fma(ps, r2, kconst(SC[i]));
+  const double sr = fma(-r * r2, ps, r);
+  double pc = kconst(CC[0]);
+#pragma unroll
+  for (int i = 1; i < 8; ++i) pc = fma(pc, r2, kconst(CC[i]));
   const double cr = fma(r2, pc, 1.0);
   const int q = ((int)k) & 3;
   s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
@@ -165,7 +162,8 @@ __device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st,
   sincos_bounded(0.5 * r, sr, chr);
   const double ur = 2.0 * sr * sr;  // 1 - cos r
   const double cr = 1.0 - 2.0 * sr * sr;
-  const bool pn = (th - r) <= 0.0, ps = (th + r) >= PI_D;
+  const double pi = kconst(PI_D);
+  const bool pn = (th - r) <= 0.0, ps = (th + r) >= pi;
   double s1, c1, s2, c2;
   sincos_bounded(th - r, s1, c1);
   sincos_bounded(th + r, s2, c2);
@@ -188,8 +186,8 @@ __device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st,
           m = 0;
         } else if (c > -1.0) {
           const double half = acos(fmin(c, 1.0)) + R.dphi;
-          if (half < PI_D) {
-            const double inv = (double)R.n * (0.5 / PI_D);
+          if (half < pi) {
+            const double inv = (double)R.n * kconst(0.5 / PI_D);
             const int jlo = (int)floor((phr - half - R.phi0) * inv);
             const int jhi = (int)ceil((phr + half - R.phi0) * inv);
             const int span = jhi - jlo + 1;
@@ -261,7 +259,8 @@ __device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, dou
                            RingSpan *rs, int *sel) {
   double zt, st;
   sincos_bounded(th, st, zt);
-  const double phr = ph - TWO_PI_D * floor(ph / TWO_PI_D);
+  const double twopi = kconst(TWO_PI_D);
+  const double phr = ph - twopi * floor(ph / twopi);
   const int K = P.K;
   double r = P.r0, rlo = 0.0, rhi = 0.0;
   int count = 0;
@@ -309,7 +308,8 @@ __device__ void neighbour_records(const PlanDev &P, double th, double ph, int la
                                   double *nb, const double *__restrict__ map) {
   double zt, st;
   sincos_bounded(th, st, zt);
-  const double phr = ph - TWO_PI_D * floor(ph / TWO_PI_D);
+  const double twopi = kconst(TWO_PI_D);
+  const double phr = ph - twopi * floor(ph / twopi);
   const int K = P.K;
   for (int a = lane; a <= K; a += WAVE) {
     double *rec = nb + a * NBF;
@@ -555,7 +555,7 @@ constexpr unsigned long long FAIL32_BITS = 0x7ff80000000f132ull;
 // not found.
 __device__ inline bool phase_a_search(const PlanDev &P, double th, double ph, int lane, double *cu,
                                       int *ci, RingSpan *rs, int *sel) {
-  const bool good = (th >= 0.0) && (th <= PI_D) && isfinite(ph);
+  const bool good = (th >= 0.0) && (th <= kconst(PI_D)) && isfinite(ph);
   if (!good) {
     if (lane == 0) atomicAdd(P.counters + CNT_BAD_INPUT, 1ull);
     return false;
@@ -686,21 +686,36 @@ __device__ __forceinline__ void rowsys_load(RowSys<NT, NR> &S, const double *mat
   }
 }
 
+// 1 / d to full precision: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
+// Step K of the row-group elimination.  d = a_KK and inv = 1 / d arrive from
+// step K - 1, which computes them as soon as column K + 1 is final so that the
+// reciprocal overlaps the rest of that step's updates.  dg keeps the pivot of
+// each of the lane's rows: r_i^2 / d_i = y_i^2 needs no square root.
 template <int NT, int NR, int K>
-__device__ __forceinline__ void rowsys_step(RowSys<NT, NR> &S, double (&dg)[NT], int x, bool &ok) {
+__device__ __forceinline__ void rowsys_step(RowSys<NT, NR> &S, double (&dg)[NT], int x, bool &ok,
+                                            double d, double inv) {
   constexpr int TK = K / 16, XK = K % 16, N = 16 * NT;
-  const double d = rbcast<XK>(S.a[TK][K]);
   ok = ok && (d > 0.0);
-  const double rs = rsqrt(d);
-  const double rs2 = rs * rs;
   double c[NT];
 #pragma unroll
-  for (int t = TK; t < NT; ++t) c[t] = (x + 16 * t > K) ? S.a[t][K] * rs2 : 0.0;
+  for (int t = TK; t < NT; ++t) c[t] = (x + 16 * t > K) ? S.a[t][K] * inv : 0.0;
+  double dn = 1.0, invn = 1.0;
   cfor<K + 1, N>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
     const double b = rbcast<j % 16>(S.a[j / 16][K]);
 #pragma unroll
     for (int t = (j / 16 > TK ? j / 16 : TK); t < NT; ++t) S.a[t][j] = fma(-c[t], b, S.a[t][j]);
+    if constexpr (j == K + 1) {
+      dn = rbcast<j % 16>(S.a[j / 16][j]);   // next pivot, final after this update
+      invn = recip(dn);
+    }
   });
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
@@ -708,33 +723,35 @@ __device__ __forceinline__ void rowsys_step(RowSys<NT, NR> &S, double (&dg)[NT],
 #pragma unroll
     for (int t = TK; t < NT; ++t) S.r[t][q] = fma(-c[t], b, S.r[t][q]);
   }
-  dg[TK] = (x == XK) ? d * rs : dg[TK];
-  if constexpr (K + 1 < N) rowsys_step<NT, NR, K + 1>(S, dg, x, ok);
+  dg[TK] = (x == XK) ? d : dg[TK];
+  if constexpr (K + 1 < N) rowsys_step<NT, NR, K + 1>(S, dg, x, ok, dn, invn);
 }
 
-// Factorise, then value = y . z and quad = y . y per point as in fp64_phase_b.
-// Results are valid in every lane of the row group; ok is uniform in the group.
+// Factorise, then value = y . z and quad = y . y per point as in fp64_phase_b
+// (y_i = r_i / L_ii, so y_i y'_i = r_i r'_i / d_i).  Results are valid in every
+// lane of the row group; ok is uniform in the group.
 template <int NT, int SPIN, int NR>
 __device__ inline bool rowsys_phase_b(RowSys<NT, NR> &S, int x, int nrow, GroupOut &o) {
   double dg[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) dg[t] = 1.0;
   bool ok = true;
-  rowsys_step<NT, NR, 0>(S, dg, x, ok);
+  const double d0 = rbcast<0>(S.a[0][0]);
+  rowsys_step<NT, NR, 0>(S, dg, x, ok, d0, recip(d0));
   double v0 = 0.0, v1 = 0.0, q0 = 0.0, q1 = 0.0;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const double inv = (x + 16 * t < nrow) ? 1.0 / dg[t] : 0.0;
-    const double y0 = S.r[t][0] * inv, y1 = S.r[t][1] * inv;
+    const double inv = (x + 16 * t < nrow) ? recip(dg[t]) : 0.0;
+    const double r0 = S.r[t][0], r1 = S.r[t][1];
     if (SPIN == 0) {
-      v0 = fma(y0, y1, v0);
-      q0 = fma(y0, y0, q0);
+      v0 = fma(r0 * r1, inv, v0);
+      q0 = fma(r0 * r0, inv, q0);
     } else {
-      const double y2 = S.r[t][NR - 1] * inv;
-      v0 = fma(y0, y2, v0);
-      v1 = fma(y1, y2, v1);
-      q0 = fma(y0, y0, q0);
-      q1 = fma(y1, y1, q1);
+      const double r2 = S.r[t][NR - 1];
+      v0 = fma(r0 * r2, inv, v0);
+      v1 = fma(r1 * r2, inv, v1);
+      q0 = fma(r0 * r0, inv, q0);
+      q1 = fma(r1 * r1, inv, q1);
     }
   }
   o.v0 = group_sum<16>(v0);
@@ -824,19 +841,24 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
     pr[q] = (prow && ip < nrow) ? rhs[ip * NR + q] : 0.0;
   }
   double dg = 1.0;
+  double pv = rbcast<0>(d[0]);
+  double iv = recip(pv);
   cfor<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    const double piv2 = rbcast<k>(d[k]);
-    ok = ok && (piv2 > 0.0);
-    const double rs = rsqrt(piv2);
-    const double rs2 = rs * rs;
-    const double cd = (x > k) ? d[k] * rs2 : 0.0;
-    const double cp = p[k] * rs2;
+    ok = ok && (pv > 0.0);
+    const double rs = rsqrt(pv);   // only scales the panel column (off the critical path)
+    const double cd = (x > k) ? d[k] * iv : 0.0;
+    const double cp = p[k] * iv;
+    double pn = 1.0, ivn = 1.0;
     cfor<k + 1, 16>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
       const double b = rbcast<k>(d[j]);
       d[j] = fma(-cd, b, d[j]);
       if constexpr (J + 1 < T) p[j] = fma(-cp, b, p[j]);
+      if constexpr (j == k + 1) {
+        pn = rbcast<j>(d[j]);   // next pivot, final after this update
+        ivn = recip(pn);
+      }
     });
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
@@ -844,8 +866,10 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
       dr[q] = fma(-cd, b, dr[q]);
       if constexpr (J + 1 < T) pr[q] = fma(-cp, b, pr[q]);
     }
-    dg = (x == k) ? piv2 * rs : dg;
+    dg = (x == k) ? pv : dg;
     p[k] = p[k] * rs;
+    pv = pn;
+    iv = ivn;
   });
   if constexpr (J + 1 < T) {
     // the panel is consumed only under `prow`; pin it here so its elimination is
@@ -855,19 +879,19 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
 #pragma unroll
     for (int q = 0; q < NR; ++q) __asm__ volatile("" ::"v"(pr[q]));
   }
-  // rows of block J are final: y = r / L_ii (counted once, by row group 0)
+  // rows of block J are final: y_i = r_i / L_ii (counted once, by row group 0)
   if (rho == 0 && ir < nrow) {
-    const double inv = 1.0 / dg;
-    const double y0 = dr[0] * inv, y1 = dr[1] * inv;
+    const double inv = recip(dg);   // y_i y'_i = r_i r'_i / d_i
+    const double r0 = dr[0], r1 = dr[1];
     if (SPIN == 0) {
-      acc.v0 = fma(y0, y1, acc.v0);
-      acc.q0 = fma(y0, y0, acc.q0);
+      acc.v0 = fma(r0 * r1, inv, acc.v0);
+      acc.q0 = fma(r0 * r0, inv, acc.q0);
     } else {
-      const double y2 = dr[NR - 1] * inv;
-      acc.v0 = fma(y0, y2, acc.v0);
-      acc.v1 = fma(y1, y2, acc.v1);
-      acc.q0 = fma(y0, y0, acc.q0);
-      acc.q1 = fma(y1, y1, acc.q1);
+      const double r2 = dr[NR - 1];
+      acc.v0 = fma(r0 * r2, inv, acc.v0);
+      acc.v1 = fma(r1 * r2, inv, acc.v1);
+      acc.q0 = fma(r0 * r0, inv, acc.q0);
+      acc.q1 = fma(r1 * r1, inv, acc.q1);
     }
   }
   if constexpr (J + 1 < T) {
@@ -1404,7 +1428,7 @@ __global__ __launch_bounds__(STENCIL_WPB * WAVE) void k_stencil(PlanDev P, const
   const int K = P.K;
   for (int64_t pt = (int64_t)blockIdx.x * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb) {
     const double th = theta[pt], ph = phi[pt];
-    const bool good = (th >= 0.0) && (th <= PI_D) && isfinite(ph);
+    const bool good = (th >= 0.0) && (th <= kconst(PI_D)) && isfinite(ph);
     bool found = false;
     if (good) found = knn_search(P, th, ph, lane, cu, ci, rs, sel);
     for (int k = lane; k < K; k += WAVE) idx[pt * K + k] = found ? (int64_t)sel[k] : -1;
