@@ -171,6 +171,69 @@ int flints_plan_reset_stats(flints_plan_t plan);
 /* Release a plan.  The caller must ensure no work using it is in flight. */
 void flints_plan_destroy(flints_plan_t plan);
 
+/*
+ * Batched execution: many interpolation jobs (different plans -- N_side, K,
+ * spin -- and target counts) in persistent fused launches.  Jobs are cut into
+ * tiles of consecutive targets; FP64 jobs (FLINTS_VAR_PAPER) of one system-size
+ * class (n <= 16, <= 32, <= 48, <= 64 rows, n = K or 2K) share one persistent
+ * launch whose blocks take tiles from a device queue, reload the job's
+ * correlation table into LDS when the job changes, and run the same per-point
+ * arithmetic as flints_interpolate (results are bit-identical to it); spin 0
+ * and spin 2 jobs mix freely within a class.  Jobs with FP32_IR or MSE-variance
+ * plans run through the single-plan path in the same stream.  Batching is an
+ * addition to the method: the paper interpolates one map at a time.
+ */
+typedef struct {
+  flints_plan_t plan;        /* borrowed; must outlive the batch */
+  const void *map;           /* as flints_interpolate */
+  const double *theta, *phi; /* device double[n] */
+  int64_t n;                 /* >= 0 */
+  void *out, *var;           /* as flints_interpolate (var nullable) */
+} flints_job_t;
+
+typedef struct flints_batch_s *flints_batch_t;
+
+enum {
+  FLINTS_BATCH_AUTOTUNE = 1   /* choose tile size and waves per block by timing
+                                 candidates on a sample of the batch at creation
+                                 (this runs kernels that write the job outputs) */
+};
+
+/*
+ * Build a batch from njobs (1 <= njobs <= 65536) job descriptors (host array,
+ * copied; the device arrays they point to are borrowed).  Allocates the device
+ * job table, tile lists and queue counters; with FLINTS_BATCH_AUTOTUNE also
+ * synchronises the device.  Returns NULL on error.
+ */
+flints_batch_t flints_batch_create(const flints_job_t *jobs, int njobs, int flags);
+
+/* Enqueue the whole batch on stream (replays the captured graph if one exists). */
+int flints_batch_run(flints_batch_t batch, void *stream);
+
+/*
+ * Capture the launch sequence of flints_batch_run into a HIP graph (queue
+ * counters are cleared by a kernel, not a memset, so replays are exact); later
+ * flints_batch_run calls launch the graph.  stream must not be capturing.
+ */
+int flints_batch_capture(flints_batch_t batch, void *stream);
+
+typedef struct {
+  int njobs;
+  int64_t points;            /* total targets */
+  int fused_jobs;            /* jobs on the persistent launches */
+  int classes;               /* persistent launches per run */
+  int tiles[4];              /* tiles per class (n <= 16, 32, 48, 64) */
+  int tile_points[4];        /* targets per tile per class (0 = class unused) */
+  int waves_per_block[4];
+  int captured;              /* 1 if runs replay a graph */
+} flints_batch_info_t;
+
+int flints_batch_info(flints_batch_t batch, flints_batch_info_t *info);
+
+/* Release a batch (its graph, tile lists and counters; not the jobs' arrays).
+ * The caller must ensure no run of it is in flight. */
+void flints_batch_destroy(flints_batch_t batch);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *flints_last_error(void);
 

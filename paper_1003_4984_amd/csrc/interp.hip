@@ -1,33 +1,8 @@
-// FLINTS interpolation kernels for gfx950 (CDNA4), double precision.
-//
-// One 64-lane wavefront owns a group of PPW = 64/G target points.  Phase A runs
-// once per point of the group with the whole wave:
-//   a2/a3  K-nearest search: rings crossing a disc of radius r around the target
-//          are listed one per lane, their pixel windows are flattened across the
-//          wave, every lane tests one candidate pixel (chord distance in FP64 from
-//          a difference vector written in the target's rotated frame), survivors
-//          are compacted into LDS, and each candidate's rank (distance, then pixel
-//          index) is counted against all others; ranks < K form the stencil.
-//   a4/a5  per-neighbour record: offset from the target, local e_theta / e_phi,
-//          gathered map values (RING order, so neighbouring targets reuse lines).
-//   a6     every pair (a, b) of {target, neighbours}: half chord s, correlation
-//          from the LDS table (cubic), spin-2 parallel-transport phases from the
-//          bearings, written as the packed lower triangle of S plus the
-//          right-hand sides (target covariances and data) in LDS.
-// Phase B: lane row i of group g holds row i of the augmented system
-// [S + nI | b | data] in registers and runs a right-looking Cholesky with the
-// pivot column broadcast through LDS; carrying the right-hand sides through the
-// elimination gives y = L^-1 b and z = L^-1 data, so
-//   value = y . z = b^T (S+nI)^-1 data   (paper Eq. best_temperature_field / major_eq)
-//   var   = sigma^2 (1 - y . y)          (paper Eq. gaussvar / gaussvar_pol)
-// without a backward solve (one is run only for the MSE variance option).
-// A failed factorisation (non-positive pivot) triggers the nugget escalation of
-// paper Sec. 2.4: bisection for the smallest shift mu with S + mu I positive
-// definite, then n = mu + eps.
-#include "plan.h"
-#include "healpix_ring.h"
-#include "table_interp.h"
-#include "kconst.h"
+// FLINTS single-plan kernels and launchers for gfx950 (CDNA4): the row-group
+// path (n <= 32), the tile path (32 < n <= 64), the register-row path (MSE
+// variance and the FP32 + refinement main pass), their fix-up passes and the
+// stencil kernel.  The device code they run lives in device.h.
+#include "device.h"
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -36,1068 +11,6 @@
 #include <utility>
 
 namespace flints {
-
-constexpr int WAVE = 64;
-constexpr int MAX_WPB = 8;      // waves per block of the interpolation kernels (launch bound 512)
-constexpr int STENCIL_WPB = 4;  // waves per block of the stencil kernel (launch bound 256)
-constexpr int CAND_CAP = 320;
-constexpr int NBF = 10;  // doubles per neighbour record
-constexpr double PI_D = 3.14159265358979323846;
-constexpr double TWO_PI_D = 6.28318530717958647692;
-
-__device__ inline void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
-__device__ inline void compiler_fence() { __asm__ volatile("" ::: "memory"); }
-__host__ __device__ inline int tri(int r) { return r * (r + 1) / 2; }
-
-// sin and cos of x for |x| <= 2 pi (colatitudes, disc radii and half
-// longitude differences).  x is reduced by the nearest multiple k of pi/2 with
-// pi/2 split into a double and its remainder (x - k*hi is exact for |k| <= 4),
-// then sin and cos of |r| <= pi/4 come from their Taylor series (truncation
-// < 1e-19).
-__device__ inline void sincos_bounded(double x, double &s, double &c) {
-  constexpr double PIO2_HI = 1.5707963267948966;      // pi/2 rounded to double
-  constexpr double PIO2_LO = 6.123233995736766e-17;   // pi/2 - PIO2_HI
-  constexpr double TWO_OVER_PI = 0.6366197723675814;
-  // sin r = r - r^3 (1/3! - r^2/5! + ... + r^14/17!), coefficients 1/(2i+1)! with signs
-  constexpr double SC[8] = {-1.0 / 355687428096000.0, 1.0 / 1307674368000.0, -1.0 / 6227020800.0,
-                            1.0 / 39916800.0, -1.0 / 362880.0, 1.0 / 5040.0, -1.0 / 120.0, 1.0 / 6.0};
-  // cos r = 1 + r^2 (-1/2! + r^2/4! - ... + r^14/16!)
-  constexpr double CC[8] = {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
-                            -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5};
-  const double k = rint(x * kconst(TWO_OVER_PI));
-  const double r = fma(-k, kconst(PIO2_LO), fma(-k, kconst(PIO2_HI), x));
-  const double r2 = r * r;
-  double ps = kconst(SC[0]);
-#pragma unroll
-  for (int i = 1; i < 8; ++i) ps = fma(ps, r2, kconst(SC[i]));
-  const double sr = fma(-r * r2, ps, r);
-  double pc = kconst(CC[0]);
-#pragma unroll
-  for (int i = 1; i < 8; ++i) pc = fma(pc, r2, kconst(CC[i]));
-  const double cr = fma(r2, pc, 1.0);
-  const int q = ((int)k) & 3;
-  s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
-  c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
-}
-
-// Broadcast a double held by lane `src` (wave-uniform index) to all lanes.
-__device__ inline double readlane_d(double v, int src) {
-  const unsigned long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
-  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
-  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
-__device__ inline float readlane_d(float v, int src) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-}
-
-// Value of `v` in row k of this lane's group (groups of G lanes).
-template <int G, typename T>
-__device__ inline T group_bcast(T v, int k, int grp) {
-  T r = readlane_d(v, k);
-#pragma unroll
-  for (int g = 1; g < WAVE / G; ++g) {
-    const T t = readlane_d(v, g * G + k);
-    r = (grp == g) ? t : r;
-  }
-  return r;
-}
-
-
-struct RingSpan {
-  double z, s, phi0, dphi;
-  long long first;
-  int n, j0, off, pad;
-};
-
-struct Layout {
-  int tab_bytes, wave_bytes;
-  int off_cu, off_ci, off_rings, off_sel, off_nb, off_mat, off_rhs, off_col, off_rbuf;
-  int matsz;
-};
-
-static inline int al16(int x) { return (x + 15) & ~15; }
-
-// Per-wave LDS: the stencils of the wave's points, then a region used first by
-// the K-nearest search (candidates, ring spans) and afterwards by the assembly
-// (one neighbour-record slot, the packed systems and right-hand sides of all
-// PPW points).  The search of every point of the group runs before any
-// assembly, so the two uses never overlap.
-static Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int NR, int min_mat = 0) {
-  Layout L;
-  L.tab_bytes = al16(ntab * nf * 8);
-  int o = 0;
-  L.off_sel = o;   o = al16(o + ppw * K * 4);
-  const int u0 = o;
-  // search view
-  int s = u0;
-  L.off_cu = s;    s = al16(s + (CAND_CAP + 4) * 8);
-  L.off_ci = s;    s = al16(s + (CAND_CAP + 4) * 4);
-  L.off_rings = s; s = al16(s + WAVE * (int)sizeof(RingSpan));
-  // assembly view
-  int a = u0;
-  L.off_nb = a;    a = al16(a + (K + 1) * NBF * 8);
-  L.matsz = std::max(n * (n + 1) / 2, min_mat);
-  L.off_mat = a;   a = al16(a + nsys * L.matsz * 8);
-  L.off_rhs = a;   a = al16(a + nsys * n * NR * 8);
-  L.off_col = a;
-  L.off_rbuf = a;  a = al16(a + nsys * 4 * 8);
-  L.wave_bytes = s > a ? s : a;
-  return L;
-}
-
-__device__ inline void count_event(unsigned long long *ctr, bool cond, int lane) {
-  unsigned long long m = __ballot(cond);
-  if (m && lane == 0) atomicAdd(ctr, (unsigned long long)__popcll(m));
-}
-
-// ---------------------------------------------------------------- a2/a3 search
-// Candidates within angle r of the target, compacted into (cu, ci).  Returns the
-// number found (entries beyond CAND_CAP are counted but not stored).
-__device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st, double phr,
-                              double r, int lane, double *cu, int *ci, RingSpan *rs) {
-  const int64_t N = P.nside;
-  double sr, chr;
-  sincos_bounded(0.5 * r, sr, chr);
-  const double ur = 2.0 * sr * sr;  // 1 - cos r
-  const double cr = 1.0 - 2.0 * sr * sr;
-  const double pi = kconst(PI_D);
-  const bool pn = (th - r) <= 0.0, ps = (th + r) >= pi;
-  double s1, c1, s2, c2;
-  sincos_bounded(th - r, s1, c1);
-  sincos_bounded(th + r, s2, c2);
-  const double zhi = pn ? 1.0 : c1;
-  const double zlo = ps ? -1.0 : c2;
-  int i0 = (int)floor(ring_coord(N, zhi)) - 1;
-  if (i0 < 1) i0 = 1;
-  int i1 = (int)ceil(ring_coord(N, zlo)) + 1;
-  if (i1 > (int)(4 * N - 1)) i1 = (int)(4 * N - 1);
-  int count = 0;
-  for (int ib = i0; ib <= i1; ib += WAVE) {
-    const int i = ib + lane;
-    int m = 0, j0 = 0;
-    if (i <= i1) {
-      const Ring R = ring_geom(N, i);
-      m = R.n;
-      if (!(pn || ps)) {
-        const double c = (cr - zt * R.z) / (st * R.s);
-        if (c > 1.0 + 1e-6) {
-          m = 0;
-        } else if (c > -1.0) {
-          const double half = acos(fmin(c, 1.0)) + R.dphi;
-          if (half < pi) {
-            const double inv = (double)R.n * kconst(0.5 / PI_D);
-            const int jlo = (int)floor((phr - half - R.phi0) * inv);
-            const int jhi = (int)ceil((phr + half - R.phi0) * inv);
-            const int span = jhi - jlo + 1;
-            if (span < R.n) {
-              j0 = jlo;
-              m = span;
-            }
-          }
-        }
-      }
-      RingSpan S;
-      S.z = R.z; S.s = R.s; S.phi0 = R.phi0; S.dphi = R.dphi;
-      S.first = R.first; S.n = R.n;
-      int jm = j0 % R.n;
-      if (jm < 0) jm += R.n;
-      S.j0 = jm;
-      S.off = 0;
-      S.pad = 0;
-      rs[lane] = S;
-    }
-    int incl = m;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const int v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-    }
-    const int total = __shfl(incl, WAVE - 1);
-    const int nrg = min(WAVE, i1 - ib + 1);
-    if (i <= i1) rs[lane].off = incl - m;
-    for (int c0 = 0; c0 < total; c0 += WAVE) {
-      const int c = c0 + lane;
-      bool keep = false;
-      double u = 0.0;
-      int pix = 0;
-      if (c < total) {
-        int lo = 0, hi = nrg - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (rs[mid].off <= c) lo = mid; else hi = mid - 1;
-        }
-        const RingSpan S = rs[lo];
-        int j = S.j0 + (c - S.off);
-        if (j >= S.n) j -= S.n;
-        const double dphi = S.phi0 + (double)j * S.dphi - phr;
-        double sh, ch;
-        sincos_bounded(0.5 * dphi, sh, ch);
-        const double sdiff = (zt - S.z) * (zt + S.z) / (S.s + st);   // s_ring - s_target
-        const double dx = sdiff - 2.0 * S.s * sh * sh;
-        const double dy = 2.0 * S.s * sh * ch;
-        const double dz = S.z - zt;
-        u = 0.5 * (dx * dx + dy * dy + dz * dz);
-        keep = (u <= ur);
-        pix = (int)(S.first + j);
-      }
-      const unsigned long long mk = __ballot(keep);
-      const int pos = count + __popcll(mk & ((1ull << lane) - 1ull));
-      if (keep && pos < CAND_CAP) {
-        cu[pos] = u;
-        ci[pos] = pix;
-      }
-      count += __popcll(mk);
-    }
-  }
-  return count;
-}
-
-// K nearest pixels of (th, ph), ascending (distance, index), into sel[0..K).
-__device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, double *cu, int *ci,
-                           RingSpan *rs, int *sel) {
-  double zt, st;
-  sincos_bounded(th, st, zt);
-  const double twopi = kconst(TWO_PI_D);
-  const double phr = ph - twopi * floor(ph / twopi);
-  const int K = P.K;
-  double r = P.r0, rlo = 0.0, rhi = 0.0;
-  int count = 0;
-  bool ok = false;
-  for (int att = 0; att < 24; ++att) {
-    count = enumerate_disc(P, th, zt, st, phr, r, lane, cu, ci, rs);
-    if (count >= K && count <= CAND_CAP) { ok = true; break; }
-    if (count < K) {
-      if (r >= P.rcap) break;
-      rlo = r;
-      r = (rhi > 0.0) ? 0.5 * (r + rhi) : fmin(1.5 * r, P.rcap);
-    } else {
-      rhi = r;
-      r = 0.5 * (rlo + r);
-    }
-  }
-  if (!ok) return false;
-  // pad to a multiple of 4 with keys that rank after every real candidate
-  const int cpad = (count + 3) & ~3;
-  if (lane < cpad - count) {
-    cu[count + lane] = __builtin_inf();
-    ci[count + lane] = 0x7fffffff;
-  }
-  for (int c = lane; c < count; c += WAVE) {
-    const double uc = cu[c];
-    const int ic = ci[c];
-    int rank = 0;
-    for (int c2 = 0; c2 < cpad; c2 += 4) {
-      const double2 ua = *(const double2 *)(cu + c2);
-      const double2 ub = *(const double2 *)(cu + c2 + 2);
-      const int4 iv = *(const int4 *)(ci + c2);
-      rank += (ua.x < uc) || (ua.x == uc && iv.x < ic);
-      rank += (ua.y < uc) || (ua.y == uc && iv.y < ic);
-      rank += (ub.x < uc) || (ub.x == uc && iv.z < ic);
-      rank += (ub.y < uc) || (ub.y == uc && iv.w < ic);
-    }
-    if (rank < K) sel[rank] = ic;
-  }
-  return true;
-}
-
-// ---------------------------------------------------------------- a4/a5 records
-template <int SPIN>
-__device__ void neighbour_records(const PlanDev &P, double th, double ph, int lane, const int *sel,
-                                  double *nb, const double *__restrict__ map) {
-  double zt, st;
-  sincos_bounded(th, st, zt);
-  const double twopi = kconst(TWO_PI_D);
-  const double phr = ph - twopi * floor(ph / twopi);
-  const int K = P.K;
-  for (int a = lane; a <= K; a += WAVE) {
-    double *rec = nb + a * NBF;
-    if (a == 0) {
-      rec[0] = 0.0; rec[1] = 0.0; rec[2] = 0.0;
-      rec[3] = zt;  rec[4] = 0.0; rec[5] = -st;
-      rec[6] = 0.0; rec[7] = 1.0;
-      rec[8] = 0.0; rec[9] = 0.0;
-    } else {
-      const int64_t p = sel[a - 1];
-      const Ring R = ring_geom(P.nside, pix_ring(P.nside, p));
-      const double dphi = R.phi0 + (double)(p - R.first) * R.dphi - phr;
-      double sh, ch;
-      sincos_bounded(0.5 * dphi, sh, ch);
-      const double sd = 2.0 * sh * ch, cd = 1.0 - 2.0 * sh * sh;
-      const double sdiff = (zt - R.z) * (zt + R.z) / (R.s + st);
-      rec[0] = sdiff - 2.0 * R.s * sh * sh;
-      rec[1] = R.s * sd;
-      rec[2] = R.z - zt;
-      rec[3] = R.z * cd; rec[4] = R.z * sd; rec[5] = -R.s;
-      rec[6] = -sd;      rec[7] = cd;
-      rec[8] = map[p];
-      rec[9] = (SPIN == 2) ? map[P.npix + p] : 0.0;
-    }
-  }
-}
-
-// ---------------------------------------------------------------- a6 assembly
-template <int SPIN, int NR>
-__device__ void assemble(const PlanDev &P, const double *tab, const double *nb, int lane,
-                         double *mat, double *rhs) {
-  const int K = P.K;
-  const int npairs = (K + 1) * (K + 2) / 2;
-  const bool paper = (P.mode == FLINTS_S2_PAPER);
-  bool range_bad = false;
-  // pair q = a (a + 1) / 2 + b, 0 <= b <= a <= K; lanes stride by WAVE through q
-  int a = 0, b = lane;
-  while (b > a) { b -= a + 1; ++a; }
-  for (int q = lane; q < npairs; q += WAVE) {
-    if (q > 0) {
-      const double *A = nb + a * NBF;
-      const double *B = nb + b * NBF;
-      if (SPIN == 0) {
-        const int ra = a - 1;
-        if (a == b) {
-          mat[tri(ra) + ra] = 1.0;
-          rhs[ra * NR + 1] = A[8];
-        } else {
-          const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
-          const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
-          double f;
-          range_bad |= !table_lookup(tab, P.ntab, 1, P.inv_h, s, &f);
-          if (b == 0) rhs[ra * NR + 0] = f;
-          else mat[tri(ra) + (b - 1)] = f;
-        }
-      } else {
-        const int ra = 2 * (a - 1);
-        if (a == b) {
-          mat[tri(ra) + ra] = 1.0;
-          mat[tri(ra + 1) + ra] = 0.0;
-          mat[tri(ra + 1) + ra + 1] = 1.0;
-          rhs[ra * NR + 2] = A[8];
-          rhs[(ra + 1) * NR + 2] = A[9];
-        } else {
-          const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
-          const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
-          double f[2];
-          range_bad |= !table_lookup(tab, P.ntab, 2, P.inv_h, s, f);
-          // bearings: e^{2 i psi} from the chord projected on each point's (e_theta, e_phi)
-          const double xa = dx * A[3] + dy * A[4] + dz * A[5];
-          const double ya = dx * A[6] + dy * A[7];
-          const double xb = dx * B[3] + dy * B[4] + dz * B[5];
-          const double yb = dx * B[6] + dy * B[7];
-          const double na = xa * xa + ya * ya, nbn = xb * xb + yb * yb;
-          const double prod = na * nbn;
-          double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
-          if (prod > 0.0) {
-            const double inv = 1.0 / prod;
-            const double ia = nbn * inv, ib = na * inv;
-            ca = (xa * xa - ya * ya) * ia; sa = 2.0 * xa * ya * ia;
-            cb = (xb * xb - yb * yb) * ib; sb = 2.0 * xb * yb * ib;
-          } else {
-            if (na > 0.0) { const double in = 1.0 / na; ca = (xa * xa - ya * ya) * in; sa = 2.0 * xa * ya * in; }
-            if (nbn > 0.0) { const double in = 1.0 / nbn; cb = (xb * xb - yb * yb) * in; sb = 2.0 * xb * yb * in; }
-          }
-          // <P_a P_b*> = xi+ e^{2i(psi_ab - psi_ba)},  <P_a P_b> = xi- e^{2i(psi_ab + psi_ba)}
-          const double gr = f[0] * (ca * cb + sa * sb), gi = f[0] * (sa * cb - ca * sb);
-          const double pr = paper ? 0.0 : f[1] * (ca * cb - sa * sb);
-          const double pim = paper ? 0.0 : f[1] * (sa * cb + ca * sb);
-          const double QQ = gr + pr, UU = gr - pr, QU = pim - gi, UQ = pim + gi;
-          if (b == 0) {
-            rhs[ra * NR + 0] = QQ;        // Cov(Q_a, Q_0)
-            rhs[(ra + 1) * NR + 0] = UQ;  // Cov(U_a, Q_0)
-            rhs[ra * NR + 1] = QU;        // Cov(Q_a, U_0)
-            rhs[(ra + 1) * NR + 1] = UU;  // Cov(U_a, U_0)
-          } else {
-            const int rb = 2 * (b - 1);
-            mat[tri(ra) + rb] = QQ;
-            mat[tri(ra) + rb + 1] = QU;
-            mat[tri(ra + 1) + rb] = UQ;
-            mat[tri(ra + 1) + rb + 1] = UU;
-          }
-        }
-      }
-    }
-    b += WAVE;
-    while (b > a) { b -= a + 1; ++a; }
-  }
-  count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
-}
-
-// ---------------------------------------------------------------- phase B
-// Full symmetric row `row` of the group's system into registers (the upper part
-// is read from the mirrored packed entry); rows past n and rows of inactive
-// groups become identity rows with zero right-hand sides, which leave the
-// factorisation of the real rows untouched.
-template <int NMAX, int NR>
-__device__ inline void load_rows(const double *mat, const double *rhs, int row, bool act, int nrow,
-                                 double (&a)[NMAX], double (&r)[NR]) {
-#pragma unroll
-  for (int j = 0; j < NMAX; ++j) {
-    const int idx = (j <= row) ? tri(row) + j : tri(j) + row;
-    // columns past n stay exactly zero in real rows (padding must not see garbage)
-    a[j] = act ? ((j < nrow) ? mat[idx] : 0.0) : (j == row ? 1.0 : 0.0);
-  }
-#pragma unroll
-  for (int q = 0; q < NR; ++q) r[q] = act ? rhs[row * NR + q] : 0.0;
-}
-
-__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
-__device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
-
-// Right-looking Cholesky of the group's rows (all NMAX steps) with the
-// right-hand sides carried along.  Every active lane updates its whole row, so
-// the trailing matrix stays symmetric and the column needed at step k equals row
-// k, held by one lane: pivot, column and the pivot row's right-hand sides are
-// broadcast with readlane (no LDS traffic).  Rows that have already pivoted do
-// not update, so at the end lane i holds row i of L (columns < i), L_ii, and in
-// its upper half A^(i)_ij = L_ji L_ii (column i of L, scaled): both triangular
-// solves are then register-local (see back_solve).  Steps are generated by
-// template recursion so every register index is a compile-time constant.
-template <typename T, int NMAX, int G, int NR, int K>
-__device__ __forceinline__ void chol_step(T (&a)[NMAX], T (&r)[NR], int row, int grp, T nug,
-                                          bool &ok, T &mydiag) {
-  const T d = group_bcast<G>(a[K], K, grp) + nug;
-  ok = ok && (d > T(0));
-  const T rs = rsqrt_t(d);
-  const T c = (row > K) ? a[K] * rs * rs : T(0);
-  // broadcasts issued four at a time, so the VALU write of each SGPR pair is
-  // separated from its first read by independent work (no hazard stalls)
-  constexpr int CH = 4;
-#pragma unroll
-  for (int j0 = K + 1; j0 < NMAX; j0 += CH) {
-    T s[CH];
-#pragma unroll
-    for (int u = 0; u < CH; ++u)
-      if (j0 + u < NMAX) s[u] = group_bcast<G>(a[j0 + u], K, grp);
-#pragma unroll
-    for (int u = 0; u < CH; ++u)
-      if (j0 + u < NMAX) a[j0 + u] = fma(-c, s[u], a[j0 + u]);
-  }
-#pragma unroll
-  for (int q = 0; q < NR; ++q) r[q] = fma(-c, group_bcast<G>(r[q], K, grp), r[q]);
-  const T piv = d * rs;
-  if (row == K) mydiag = piv;
-  a[K] = (row == K) ? piv : ((row > K) ? a[K] * rs : a[K]);
-  if constexpr (K + 1 < NMAX) chol_step<T, NMAX, G, NR, K + 1>(a, r, row, grp, nug, ok, mydiag);
-}
-
-template <int NMAX, int G, int NR, typename T>
-__device__ __forceinline__ bool chol_rows(T (&a)[NMAX], T (&r)[NR], int row, int grp, T nug,
-                                          T &mydiag) {
-  bool ok = true;
-  mydiag = T(1);
-  chol_step<T, NMAX, G, NR, 0>(a, r, row, grp, nug, ok, mydiag);
-  return ok;
-}
-
-// Backward substitution L^T w = y after chol_rows: lane i accumulates
-// sum_{k>i} A^(i)_ik w_k = L_ii sum_{k>i} L_ki w_k from its own upper half as the
-// w_k (k descending) are broadcast, then w_i = (y_i - acc_i / L_ii) / L_ii.
-template <typename T, int NMAX, int G, int NW, int K>
-__device__ __forceinline__ void back_step(const T (&a)[NMAX], const T (&y)[NW], T inv, int row,
-                                          int grp, T (&acc)[NW], T (&w)[NW]) {
-#pragma unroll
-  for (int q = 0; q < NW; ++q) {
-    const T t = (y[q] - acc[q] * inv) * inv;
-    const T wk = group_bcast<G>(t, K, grp);
-    if (row == K) w[q] = wk;
-    acc[q] = (row < K) ? fma(a[K], wk, acc[q]) : acc[q];
-  }
-  if constexpr (K > 0) back_step<T, NMAX, G, NW, K - 1>(a, y, inv, row, grp, acc, w);
-}
-
-template <int NMAX, int G, int NW, typename T>
-__device__ __forceinline__ void back_solve(const T (&a)[NMAX], const T (&y)[NW], T diag, int row,
-                                           int grp, T (&w)[NW]) {
-  T acc[NW], inv = T(1) / diag;
-#pragma unroll
-  for (int q = 0; q < NW; ++q) { acc[q] = T(0); w[q] = T(0); }
-  back_step<T, NMAX, G, NW, NMAX - 1>(a, y, inv, row, grp, acc, w);
-}
-
-// Forward substitution L t = v with L in the lanes' lower halves (row i holds
-// L_ij, j < i), pivots broadcast in increasing order.
-template <typename T, int NMAX, int G, int NW, int K>
-__device__ __forceinline__ void fwd_step(const T (&a)[NMAX], T (&v)[NW], T inv, int row, int grp,
-                                         T (&t)[NW]) {
-#pragma unroll
-  for (int q = 0; q < NW; ++q) {
-    const T tk = group_bcast<G>(v[q] * inv, K, grp);
-    if (row == K) t[q] = tk;
-    v[q] = (row > K) ? fma(-a[K], tk, v[q]) : v[q];
-  }
-  if constexpr (K + 1 < NMAX) fwd_step<T, NMAX, G, NW, K + 1>(a, v, inv, row, grp, t);
-}
-
-template <int NMAX, int G, int NW, typename T>
-__device__ __forceinline__ void fwd_solve(const T (&a)[NMAX], T (&v)[NW], T diag, int row,
-                                          int grp, T (&t)[NW]) {
-  const T inv = T(1) / diag;
-#pragma unroll
-  for (int q = 0; q < NW; ++q) t[q] = T(0);
-  fwd_step<T, NMAX, G, NW, 0>(a, v, inv, row, grp, t);
-}
-
-template <int G>
-__device__ inline double group_sum(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
-}
-
-// ---------------------------------------------------------------- kernel
-// Output values that tag a point for the fix-up pass (quiet NaNs with private
-// payloads): FP64 factorisation failed (nugget escalation needed), or the FP32
-// factorisation / refinement was rejected (recompute in FP64).
-constexpr unsigned long long FAIL64_BITS = 0x7ff80000000f1a7ull;
-constexpr unsigned long long FAIL32_BITS = 0x7ff80000000f132ull;
-
-// Phase A, first half, for one point with the whole wave: validity and the
-// K-nearest search.  Returns false if the point is invalid or its stencil was
-// not found.
-__device__ inline bool phase_a_search(const PlanDev &P, double th, double ph, int lane, double *cu,
-                                      int *ci, RingSpan *rs, int *sel) {
-  const bool good = (th >= 0.0) && (th <= kconst(PI_D)) && isfinite(ph);
-  if (!good) {
-    if (lane == 0) atomicAdd(P.counters + CNT_BAD_INPUT, 1ull);
-    return false;
-  }
-  if (!knn_search(P, th, ph, lane, cu, ci, rs, sel)) {
-    if (lane == 0) atomicAdd(P.counters + CNT_SEARCH_FAIL, 1ull);
-    return false;
-  }
-  return true;
-}
-
-// Phase A, second half: neighbour records and the covariance assembly.
-template <int SPIN, int NR>
-__device__ inline void phase_a_build(const PlanDev &P, const double *tab,
-                                     const double *__restrict__ map, double th, double ph, int lane,
-                                     const int *sel, double *nb, double *mat, double *rhs) {
-  neighbour_records<SPIN>(P, th, ph, lane, sel, nb, map);
-  assemble<SPIN, NR>(P, tab, nb, lane, mat, rhs);
-}
-
-struct WaveBufs {
-  double *cu; int *ci; RingSpan *rs; int *sel; double *nb; double *mat; double *rhs; double *rbuf;
-};
-
-__device__ inline WaveBufs wave_bufs(char *lds, const Layout &L, int wave) {
-  char *wb = lds + L.tab_bytes + wave * L.wave_bytes;
-  WaveBufs B;
-  B.cu = (double *)(wb + L.off_cu);
-  B.ci = (int *)(wb + L.off_ci);
-  B.rs = (RingSpan *)(wb + L.off_rings);
-  B.sel = (int *)(wb + L.off_sel);
-  B.nb = (double *)(wb + L.off_nb);
-  B.mat = (double *)(wb + L.off_mat);
-  B.rhs = (double *)(wb + L.off_rhs);
-  B.rbuf = (double *)(wb + L.off_rbuf);
-  return B;
-}
-
-__device__ inline const double *load_table(char *lds, const PlanDev &P) {
-  const int ntabd = P.ntab * P.nfun;
-  for (int i = threadIdx.x; i < ntabd; i += blockDim.x) ((double *)lds)[i] = P.tab[i];
-  __syncthreads();
-  return (const double *)lds;
-}
-
-template <int G>
-__device__ inline double group_min(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
-  return v;
-}
-template <int G>
-__device__ inline double group_max(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
-  return v;
-}
-
-// Per-group results handed to store_point.
-struct GroupOut {
-  double v0, v1, qd0, qd1, w0, w1;
-};
-
-// ---------------------------------------------------------------- phase B, n <= 32
-// One system per 16-lane row of the wave (four points per wave).  Lane x of a
-// row group holds the lower-triangular rows x + 16 t (t < NT) of its point, row
-// x + 16 t in a[t][0 .. 16 t + 15] with the column as register index, plus the
-// right-hand sides of those rows.  The right-looking elimination needs, at step
-// k, the pivot a_kk and column k (a_jk of every row j > k): both sit in one lane
-// of the same 16-lane row, so each value reaches the whole row group through a
-// DPP row broadcast (one VALU move per value, no scalar registers).  The pivot
-// row is never scaled: row i is updated with c_i = a_ik / a_kk times the raw
-// a_jk, and the right-hand sides likewise, so after the last step r_i = L_ii y_i.
-
-// Value of v held by lane K of this lane's 16-lane row.
-template <int K>
-__device__ __forceinline__ double rbcast(double v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xf, 0xf, false);  // row_newbcast:K
-}
-
-// Compile-time loop: f(integral_constant<int, i>) for i in [B, E).
-template <int B, int E, typename F>
-__device__ __forceinline__ void cfor(F &&f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    cfor<B + 1, E>(f);
-  }
-}
-
-template <int NT, int NR>
-struct RowSys {
-  double a[NT][16 * NT];   // a[t][j] used for j < 16 (t + 1)
-  double r[NT][NR];
-};
-
-// Identity rows with zero right-hand sides (inactive points and padding rows
-// factorise trivially and leave the real rows untouched).
-template <int NT, int NR>
-__device__ __forceinline__ void rowsys_identity(RowSys<NT, NR> &S, int x) {
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-#pragma unroll
-    for (int j = 0; j < 16 * (t + 1); ++j) S.a[t][j] = (j == x + 16 * t) ? 1.0 : 0.0;
-#pragma unroll
-    for (int q = 0; q < NR; ++q) S.r[t][q] = 0.0;
-  }
-}
-
-// Rows x + 16 t of the packed system (lower triangle, row-major) into registers,
-// with the nugget added on the diagonal.  Entries right of the diagonal are zero.
-template <int NT, int NR>
-__device__ __forceinline__ void rowsys_load(RowSys<NT, NR> &S, const double *mat, const double *rhs,
-                                            int x_in, int nrow, double nug) {
-  int x = x_in;
-  __asm__ volatile("" : "+v"(x));   // row-dependent LDS addresses stay out of LICM
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int i = x + 16 * t;
-    const bool real = i < nrow;
-    const int ic = real ? i : 0;
-#pragma unroll
-    for (int j = 0; j < 16 * (t + 1); ++j) {
-      const double v = mat[tri(ic) + (j < ic ? j : ic)];
-      S.a[t][j] = real ? (j < i ? v : (j == i ? v + nug : 0.0)) : (j == i ? 1.0 : 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) S.r[t][q] = real ? rhs[ic * NR + q] : 0.0;
-  }
-}
-
-// 1 / d to full precision: the hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double recip(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  r = fma(r, fma(-d, r, 1.0), r);
-  return r;
-}
-
-// Step K of the row-group elimination.  d = a_KK and inv = 1 / d arrive from
-// step K - 1, which computes them as soon as column K + 1 is final so that the
-// reciprocal overlaps the rest of that step's updates.  dg keeps the pivot of
-// each of the lane's rows: r_i^2 / d_i = y_i^2 needs no square root.
-template <int NT, int NR, int K>
-__device__ __forceinline__ void rowsys_step(RowSys<NT, NR> &S, double (&dg)[NT], int x, bool &ok,
-                                            double d, double inv) {
-  constexpr int TK = K / 16, XK = K % 16, N = 16 * NT;
-  ok = ok && (d > 0.0);
-  double c[NT];
-#pragma unroll
-  for (int t = TK; t < NT; ++t) c[t] = (x + 16 * t > K) ? S.a[t][K] * inv : 0.0;
-  double dn = 1.0, invn = 1.0;
-  cfor<K + 1, N>([&](auto jc) {
-    constexpr int j = decltype(jc)::value;
-    const double b = rbcast<j % 16>(S.a[j / 16][K]);
-#pragma unroll
-    for (int t = (j / 16 > TK ? j / 16 : TK); t < NT; ++t) S.a[t][j] = fma(-c[t], b, S.a[t][j]);
-    if constexpr (j == K + 1) {
-      dn = rbcast<j % 16>(S.a[j / 16][j]);   // next pivot, final after this update
-      invn = recip(dn);
-    }
-  });
-#pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    const double b = rbcast<XK>(S.r[TK][q]);
-#pragma unroll
-    for (int t = TK; t < NT; ++t) S.r[t][q] = fma(-c[t], b, S.r[t][q]);
-  }
-  dg[TK] = (x == XK) ? d : dg[TK];
-  if constexpr (K + 1 < N) rowsys_step<NT, NR, K + 1>(S, dg, x, ok, dn, invn);
-}
-
-// Factorise, then value = y . z and quad = y . y per point as in fp64_phase_b
-// (y_i = r_i / L_ii, so y_i y'_i = r_i r'_i / d_i).  Results are valid in every
-// lane of the row group; ok is uniform in the group.
-template <int NT, int SPIN, int NR>
-__device__ inline bool rowsys_phase_b(RowSys<NT, NR> &S, int x, int nrow, GroupOut &o) {
-  double dg[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) dg[t] = 1.0;
-  bool ok = true;
-  const double d0 = rbcast<0>(S.a[0][0]);
-  rowsys_step<NT, NR, 0>(S, dg, x, ok, d0, recip(d0));
-  double v0 = 0.0, v1 = 0.0, q0 = 0.0, q1 = 0.0;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const double inv = (x + 16 * t < nrow) ? recip(dg[t]) : 0.0;
-    const double r0 = S.r[t][0], r1 = S.r[t][1];
-    if (SPIN == 0) {
-      v0 = fma(r0 * r1, inv, v0);
-      q0 = fma(r0 * r0, inv, q0);
-    } else {
-      const double r2 = S.r[t][NR - 1];
-      v0 = fma(r0 * r2, inv, v0);
-      v1 = fma(r1 * r2, inv, v1);
-      q0 = fma(r0 * r0, inv, q0);
-      q1 = fma(r1 * r1, inv, q1);
-    }
-  }
-  o.v0 = group_sum<16>(v0);
-  o.qd0 = group_sum<16>(q0);
-  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
-  if (SPIN != 0) {
-    o.v1 = group_sum<16>(v1);
-    o.qd1 = group_sum<16>(q1);
-  }
-  return ok;
-}
-
-// ---------------------------------------------------------------- phase B, 32 < n <= 64
-// Blocked right-looking Cholesky of one system per wave on 16 x 16 tiles.  For
-// block column J the wave's four 16-lane row groups each take one block row
-// J + rho (rho = 0 .. 3): every group holds a replica of the diagonal tile (row x
-// of it in lane x) and its own panel tile, and eliminates the 16 columns with
-// DPP row broadcasts as in the row-group path, which factors the diagonal tile
-// and solves the panel L_rJ = A_rJ L_JJ^-T at once.  The trailing tiles then
-// take A_rs -= L_rJ L_sJ^T on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
-// with the panels staged through LDS into the MFMA operand layout.  Trailing
-// tiles live in registers in the MFMA accumulator layout: lane l, element v
-// holds tile entry (4 v + l / 16, l % 16).  The right-hand sides ride along in
-// the elimination and return to LDS between block columns.
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-constexpr int TSTR = 18;             // row stride (doubles) of a staged 16 x 16 tile
-constexpr int TILE_D = 16 * TSTR;    // doubles per staged tile
-
-template <int T>
-struct TileSys {
-  dbl4 c[T][T];   // c[r][s], 1 <= s <= r < T
-};
-
-// S + nI entry (i, j) of the packed system, identity beyond n.
-__device__ __forceinline__ double packed_entry(const double *mat, int i, int j, int nrow, double nug) {
-  const bool real = (i < nrow) && (j < nrow);
-  const int hi = i > j ? i : j, lo = i > j ? j : i;
-  const double v = mat[real ? tri(hi) + lo : 0];
-  return real ? (i == j ? v + nug : v) : (i == j ? 1.0 : 0.0);
-}
-
-template <int T>
-__device__ __forceinline__ void tiles_load(TileSys<T> &S, const double *mat, int l, int nrow, double nug) {
-#pragma unroll
-  for (int r = 1; r < T; ++r)
-#pragma unroll
-    for (int s = 1; s <= r; ++s)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        S.c[r][s][v] = packed_entry(mat, 16 * r + 4 * v + (l >> 4), 16 * s + (l & 15), nrow, nug);
-}
-
-struct TileAcc {
-  double v0, v1, q0, q1;
-};
-
-template <int T, int SPIN, int NR, int J>
-__device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rhs, const double *mat,
-                                          int l, int nrow, double nug, TileAcc &acc, bool &ok) {
-  const int rho = l >> 4, x = l & 15;
-  const int rp = J + rho;                       // block row of this row group
-  const bool prow = (rho > 0) && (rp < T);      // group carries a panel tile
-  double d[16], p[16], dr[NR], pr[NR];
-  if constexpr (J == 0) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      d[j] = packed_entry(mat, x, j, nrow, nug);
-      p[j] = prow ? packed_entry(mat, 16 * rp + x, j, nrow, nug) : 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int r = J; r < T; ++r)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) scr[(r - J) * TILE_D + (4 * v + rho) * TSTR + x] = S.c[r][J][v];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      d[j] = scr[x * TSTR + j];
-      p[j] = prow ? scr[rho * TILE_D + x * TSTR + j] : 0.0;
-    }
-  }
-  const int ir = 16 * J + x, ip = 16 * rp + x;
-#pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    dr[q] = (ir < nrow) ? rhs[ir * NR + q] : 0.0;
-    pr[q] = (prow && ip < nrow) ? rhs[ip * NR + q] : 0.0;
-  }
-  double dg = 1.0;
-  double pv = rbcast<0>(d[0]);
-  double iv = recip(pv);
-  cfor<0, 16>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    ok = ok && (pv > 0.0);
-    const double rs = rsqrt(pv);   // only scales the panel column (off the critical path)
-    const double cd = (x > k) ? d[k] * iv : 0.0;
-    const double cp = p[k] * iv;
-    double pn = 1.0, ivn = 1.0;
-    cfor<k + 1, 16>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      const double b = rbcast<k>(d[j]);
-      d[j] = fma(-cd, b, d[j]);
-      if constexpr (J + 1 < T) p[j] = fma(-cp, b, p[j]);
-      if constexpr (j == k + 1) {
-        pn = rbcast<j>(d[j]);   // next pivot, final after this update
-        ivn = recip(pn);
-      }
-    });
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const double b = rbcast<k>(dr[q]);
-      dr[q] = fma(-cd, b, dr[q]);
-      if constexpr (J + 1 < T) pr[q] = fma(-cp, b, pr[q]);
-    }
-    dg = (x == k) ? pv : dg;
-    p[k] = p[k] * rs;
-    pv = pn;
-    iv = ivn;
-  });
-  if constexpr (J + 1 < T) {
-    // the panel is consumed only under `prow`; pin it here so its elimination is
-    // not sunk into that branch (which would keep every broadcast value live)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) __asm__ volatile("" ::"v"(p[j]));
-#pragma unroll
-    for (int q = 0; q < NR; ++q) __asm__ volatile("" ::"v"(pr[q]));
-  }
-  // rows of block J are final: y_i = r_i / L_ii (counted once, by row group 0)
-  if (rho == 0 && ir < nrow) {
-    const double inv = recip(dg);   // y_i y'_i = r_i r'_i / d_i
-    const double r0 = dr[0], r1 = dr[1];
-    if (SPIN == 0) {
-      acc.v0 = fma(r0 * r1, inv, acc.v0);
-      acc.q0 = fma(r0 * r0, inv, acc.q0);
-    } else {
-      const double r2 = dr[NR - 1];
-      acc.v0 = fma(r0 * r2, inv, acc.v0);
-      acc.v1 = fma(r1 * r2, inv, acc.v1);
-      acc.q0 = fma(r0 * r0, inv, acc.q0);
-      acc.q1 = fma(r1 * r1, inv, acc.q1);
-    }
-  }
-  if constexpr (J + 1 < T) {
-    if (prow && ip < nrow) {
-#pragma unroll
-      for (int q = 0; q < NR; ++q) rhs[ip * NR + q] = pr[q];
-    }
-    // panels L_rJ (r > J) to LDS, then into the MFMA operand layout:
-    // fr[r][m] at lane l = L_rJ(l % 16, 4 m + l / 16)
-    if (prow) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) scr[(rho - 1) * TILE_D + x * TSTR + j] = p[j];
-    }
-    double fr[T][4];
-#pragma unroll
-    for (int r = J + 1; r < T; ++r)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) fr[r][m] = scr[(r - J - 1) * TILE_D + x * TSTR + 4 * m + rho];
-#pragma unroll
-    for (int r = J + 1; r < T; ++r)
-#pragma unroll
-      for (int s = J + 1; s <= r; ++s)
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          S.c[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fr[r][m], fr[s][m], S.c[r][s], 0, 0, 0);
-    tile_step<T, SPIN, NR, J + 1>(S, scr, rhs, mat, l, nrow, nug, acc, ok);
-  }
-}
-
-// Factorise the wave's system (packed in mat, right-hand sides in rhs) and
-// return value / quad sums as fp64_phase_b does.  scr may overlay mat (mat is
-// read in full before the first staged tile is written); rhs is overwritten.
-template <int T, int SPIN, int NR>
-__device__ inline bool tile_phase_b(const double *mat, double *rhs, double *scr, int lane_in, int nrow,
-                                    double nug, GroupOut &o) {
-  int l = lane_in;
-  __asm__ volatile("" : "+v"(l));   // lane-dependent LDS addresses stay out of LICM
-  TileSys<T> S;
-  tiles_load<T>(S, mat, l, nrow, nug);
-  TileAcc acc{0.0, 0.0, 0.0, 0.0};
-  bool ok = true;
-  tile_step<T, SPIN, NR, 0>(S, scr, rhs, mat, l, nrow, nug, acc, ok);
-  o.v0 = group_sum<WAVE>(acc.v0);
-  o.qd0 = group_sum<WAVE>(acc.q0);
-  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
-  if (SPIN != 0) {
-    o.v1 = group_sum<WAVE>(acc.v1);
-    o.qd1 = group_sum<WAVE>(acc.q1);
-  }
-  return ok;
-}
-
-// FP64 phase B: factorise S + nI with the right-hand sides carried, then
-// value = y.z and quad = y.y per point (y = L^-1 b, z = L^-1 data); with MSE
-// also |w|^2 for w = L^-T y (register-local backward solve).
-template <int NMAX, int G, int SPIN, int NR, bool MSE>
-__device__ inline bool fp64_phase_b(const double *mat, const double *rhs, int row, int grp,
-                                    bool ract, int nrow, double nug, GroupOut &o) {
-  constexpr int NW = (SPIN == 0) ? 1 : 2;
-  double a[NMAX];
-  double r[NR];
-  load_rows<NMAX, NR>(mat, rhs, row, ract, nrow, a, r);
-  double diag;
-  const bool ok = chol_rows<NMAX, G, NR>(a, r, row, grp, nug, diag);
-  const double inv = 1.0 / diag;
-  const double y0 = ract ? r[0] * inv : 0.0;
-  const double y1 = ract ? r[1] * inv : 0.0;
-  const double y2 = (ract && NR > 2) ? r[NR - 1] * inv : 0.0;
-  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
-  if (SPIN == 0) {
-    o.v0 = group_sum<G>(y0 * y1);
-    o.qd0 = group_sum<G>(y0 * y0);
-  } else {
-    o.v0 = group_sum<G>(y0 * y2);
-    o.v1 = group_sum<G>(y1 * y2);
-    o.qd0 = group_sum<G>(y0 * y0);
-    o.qd1 = group_sum<G>(y1 * y1);
-  }
-  if (MSE) {
-    double yy[NW], w[NW];
-    yy[0] = y0;
-    if (NW > 1) yy[NW - 1] = y1;
-    back_solve<NMAX, G, NW>(a, yy, diag, row, grp, w);
-    o.w0 = group_sum<G>(ract ? w[0] * w[0] : 0.0);
-    if (NW > 1) o.w1 = group_sum<G>(ract ? w[NW - 1] * w[NW - 1] : 0.0);
-  }
-  return ok;
-}
-
-// FP64 residual res = b - (S + nI) w for the NW right-hand sides, S read from the
-// packed system in LDS and w_j broadcast from row j.
-template <int NMAX, int G, int NW, int NR>
-__device__ inline void residual64(const double *mat, const double *rhs, int row_in, bool ract, int nrow,
-                                  double nug, const double (&w)[NW], int grp, double (&res)[NW]) {
-  int row = row_in;
-  __asm__ volatile("" : "+v"(row));   // recompute the row addresses here instead of keeping them live
-#pragma unroll
-  for (int q = 0; q < NW; ++q) res[q] = ract ? rhs[row * NR + q] - nug * w[q] : 0.0;
-#pragma unroll
-  for (int j = 0; j < NMAX; ++j) {
-    const int idx = (j <= row) ? tri(row) + j : tri(j) + row;
-    const double sij = (ract && j < nrow) ? mat[idx] : 0.0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) res[q] = fma(-sij, group_bcast<G>(w[q], j, grp), res[q]);
-    if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
-  }
-}
-
-// FP32 + refinement phase B: covariance entries stay FP64 in LDS;
-// S + nI is rounded to FP32 and factorised, w = (S + nI)^-1 b is solved in FP32,
-// one refinement step uses the FP64 residual and an FP32 correction solve, and
-// value / variance use FP64 accumulation with the final FP64 residual r:
-// var = sigma^2 (1 - b.w - w.r) (stationary in w).  The point is rejected (and
-// recomputed in FP64) if the FP32 factorisation fails, if min L_kk / max L_kk is
-// below the pivot-ratio threshold, or if |dw| > refine_tol |w|.
-template <int NMAX, int G, int SPIN, int NR, bool MSE>
-__device__ inline bool fp32_phase_b(const PlanDev &P, const double *mat, const double *rhs, int row_in,
-                                    int grp, bool ract, int nrow, double nug, GroupOut &o) {
-  constexpr int NW = (SPIN == 0) ? 1 : 2;
-  int row = row_in;
-  __asm__ volatile("" : "+v"(row));
-  float a[NMAX];
-  float rb[NW];
-#pragma unroll
-  for (int j = 0; j < NMAX; ++j) {
-    const int idx = (j <= row) ? tri(row) + j : tri(j) + row;
-    a[j] = ract ? ((j < nrow) ? (float)mat[idx] : 0.0f) : (j == row ? 1.0f : 0.0f);
-  }
-#pragma unroll
-  for (int q = 0; q < NW; ++q) rb[q] = ract ? (float)rhs[row * NR + q] : 0.0f;
-  float diag;
-  bool ok = chol_rows<NMAX, G, NW>(a, rb, row, grp, (float)nug, diag);
-  const double dmin = group_min<G>(ract ? (double)diag : 1e300);
-  const double dmax = group_max<G>(ract ? (double)diag : 0.0);
-  ok = ok && (dmin >= P.pivot_ratio_min * dmax);
-  float y[NW], w32[NW];
-#pragma unroll
-  for (int q = 0; q < NW; ++q) y[q] = rb[q] / diag;
-  back_solve<NMAX, G, NW>(a, y, diag, row, grp, w32);
-  double w[NW], res[NW];
-#pragma unroll
-  for (int q = 0; q < NW; ++q) w[q] = ract ? (double)w32[q] : 0.0;
-  residual64<NMAX, G, NW, NR>(mat, rhs, row, ract, nrow, nug, w, grp, res);
-  float rv[NW], t[NW], dw[NW];
-#pragma unroll
-  for (int q = 0; q < NW; ++q) rv[q] = (float)res[q];
-  fwd_solve<NMAX, G, NW>(a, rv, diag, row, grp, t);
-  back_solve<NMAX, G, NW>(a, t, diag, row, grp, dw);
-  double dn = 0.0, wn = 0.0;
-#pragma unroll
-  for (int q = 0; q < NW; ++q) {
-    w[q] = ract ? w[q] + (double)dw[q] : 0.0;
-    dn += ract ? (double)dw[q] * (double)dw[q] : 0.0;
-    wn += w[q] * w[q];
-  }
-  dn = group_sum<G>(dn);
-  wn = group_sum<G>(wn);
-  ok = ok && (dn <= P.refine_tol * P.refine_tol * wn) && isfinite(dn);
-  residual64<NMAX, G, NW, NR>(mat, rhs, row, ract, nrow, nug, w, grp, res);
-  const double d = ract ? rhs[row * NR + NR - 1] : 0.0;
-  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
-  const double b0 = ract ? rhs[row * NR + 0] : 0.0;
-  o.v0 = group_sum<G>(w[0] * d);
-  o.qd0 = group_sum<G>(w[0] * (b0 + res[0]));
-  if (MSE) o.w0 = group_sum<G>(w[0] * w[0]);
-  if (NW > 1) {
-    const double b1 = ract ? rhs[row * NR + 1] : 0.0;
-    o.v1 = group_sum<G>(w[NW - 1] * d);
-    o.qd1 = group_sum<G>(w[NW - 1] * (b1 + res[NW - 1]));
-    if (MSE) o.w1 = group_sum<G>(w[NW - 1] * w[NW - 1]);
-  }
-  return ok;
-}
-
-// Writes the outputs of point pt (called by lane row == 0 of its group).
-// `tag` marks a rejected point for the fix-up pass.
-template <int SPIN>
-__device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool gact, bool ok,
-                                   unsigned long long tag, const GroupOut &o, double nug, bool mse,
-                                   double *out, double *var) {
-  const double nan = __builtin_nan("");
-  const double s2 = P.sigma2;
-  const bool good = gact && ok;
-  const double bad = (gact && !ok) ? __longlong_as_double((long long)tag) : nan;
-  if (SPIN == 0) {
-    double vv = s2 * (1.0 - o.qd0);
-    if (mse) vv -= s2 * nug * o.w0;
-    if (good && vv < 0.0) { atomicAdd(P.counters + CNT_CLAMPED_VAR, 1ull); vv = 0.0; }
-    out[pt] = good ? o.v0 : bad;
-    if (var) var[pt] = good ? vv : nan;
-  } else {
-    double vq = s2 * (1.0 - o.qd0), vu = s2 * (1.0 - o.qd1);
-    if (mse) { vq -= s2 * nug * o.w0; vu -= s2 * nug * o.w1; }
-    if (good && (vq < 0.0 || vu < 0.0)) {
-      atomicAdd(P.counters + CNT_CLAMPED_VAR, 1ull);
-      vq = fmax(vq, 0.0);
-      vu = fmax(vu, 0.0);
-    }
-    out[pt] = good ? o.v0 : bad;
-    out[n + pt] = good ? o.v1 : bad;
-    if (var) {
-      var[pt] = good ? vq : nan;
-      var[n + pt] = good ? vu : nan;
-    }
-  }
-}
 
 // Main pass over all targets (FP32 selects the FP32 + refinement phase B).
 template <int NMAX, int G, int SPIN, bool MSE, bool FP32>
@@ -1244,8 +157,6 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs(PlanDev P, const d
                                                    const double *__restrict__ phi, int64_t n,
                                                    double *__restrict__ out,
                                                    double *__restrict__ var, Layout L) {
-  constexpr int PPW = 4;
-  constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
   const double *tab = load_table(lds, P);
@@ -1253,69 +164,10 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs(PlanDev P, const d
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
-  const int nrow = P.n;
-  const int K = P.K;
-  const int64_t ngroups = (n + PPW - 1) / PPW;
-  const int grp = lane >> 4;
-  const int x = lane & 15;
-  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
-
-  for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb) {
-    unsigned act_mask = 0;
-#pragma unroll 1
-    for (int q = 0; q < PPW; ++q) {
-      const int64_t pt = g * PPW + q;
-      if (pt >= n) break;
-      if (phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K))
-        act_mask |= 1u << q;
-    }
-    RowSys<NT, NR> S;
-    rowsys_identity(S, x);
-#pragma unroll 1
-    for (int q = 0; q < PPW; ++q) {
-      if (!((act_mask >> q) & 1u)) continue;
-      const int64_t pt = g * PPW + q;
-      phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel + q * K, B.nb, B.mat,
-                              B.rhs);
-      if (grp == q) rowsys_load(S, B.mat, B.rhs, x, nrow, nug);
-    }
-    GroupOut o;
-    const bool ok = rowsys_phase_b<NT, SPIN, NR>(S, x, nrow, o);
-    if (x == 0) {
-      const int64_t pt = g * PPW + grp;
-      if (pt < n)
-        store_point<SPIN>(P, pt, n, (act_mask >> grp) & 1u, ok, FAIL64_BITS, o, nug, false, out, var);
-    }
-  }
+  const int64_t ngroups = (n + 3) / 4;
+  for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb)
+    group_rs<NT, SPIN>(P, tab, map, theta, phi, n, out, var, B, g * 4, lane);
 }
-
-// Phase-B engines of the fix-up pass: solve the tagged point (searched and
-// assembled into the wave's first system buffer) with nugget nug, using
-// exactly the arithmetic of the matching main pass.  `first` is false when an
-// earlier attempt may have overwritten the assembled system.
-template <int NT, int SPIN>
-struct RowGroupEngine {
-  static constexpr int NR = (SPIN == 0) ? 2 : 3;
-  __device__ static bool solve(const PlanDev &P, const double *, const double *, double, double, int lane,
-                               const WaveBufs &B, bool found, bool, double nug, GroupOut &o) {
-    RowSys<NT, NR> S;
-    rowsys_identity(S, lane & 15);
-    if (found && (lane >> 4) == 0) rowsys_load(S, B.mat, B.rhs, lane & 15, P.n, nug);
-    return __all(rowsys_phase_b<NT, SPIN, NR>(S, lane & 15, P.n, o));
-  }
-};
-
-template <int T, int SPIN>
-struct TileEngine {
-  static constexpr int NR = (SPIN == 0) ? 2 : 3;
-  __device__ static bool solve(const PlanDev &P, const double *tab, const double *map, double th,
-                               double ph, int lane, const WaveBufs &B, bool found, bool first,
-                               double nug, GroupOut &o) {
-    if (!found) return true;
-    if (!first) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
-    return __all(tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o));
-  }
-};
 
 // Fix-up pass of the row-group and tile paths (same policy as k_escalate).
 template <class Eng, int SPIN>
@@ -1324,7 +176,6 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_fixup(PlanDev P, const doubl
                                                const double *__restrict__ phi, int64_t n,
                                                double *__restrict__ out,
                                                double *__restrict__ var, Layout L) {
-  constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
   const double *tab = load_table(lds, P);
@@ -1332,53 +183,9 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_fixup(PlanDev P, const doubl
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
-  const int nrow = P.n;
-  const double nug0 = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
   const int64_t nchunks = (n + WAVE - 1) / WAVE;
-  for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb) {
-    const int64_t p0 = ch * WAVE + lane;
-    const unsigned long long bits =
-        p0 < n ? (unsigned long long)__double_as_longlong(out[p0]) : 0ull;
-    const bool t64 = bits == FAIL64_BITS, t32 = bits == FAIL32_BITS;
-    unsigned long long mask = __ballot(t64 || t32);
-    const unsigned long long m32 = __ballot(t32);
-    while (mask) {
-      const int bit = __ffsll((long long)mask) - 1;
-      mask &= mask - 1ull;
-      const bool from32 = (m32 >> bit) & 1ull;
-      const int64_t pt = ch * WAVE + bit;
-      const double th = theta[pt], ph = phi[pt];
-      const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
-      if (found) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
-      GroupOut o;
-      double nug = nug0;
-      bool ok = false, first = true;
-      if (from32) {
-        ok = Eng::solve(P, tab, map, th, ph, lane, B, found, first, nug, o);
-        first = false;
-        if (lane == 0) atomicAdd(P.counters + CNT_FP64_FALLBACK, 1ull);
-      }
-      if (!ok) {
-        double lo = nug0, hi = (double)nrow + 1.0;
-#pragma unroll 1
-        for (int it = 0; it < 64; ++it) {
-          const double mu = 0.5 * (lo + hi);
-          GroupOut tmp;
-          const bool ok2 = Eng::solve(P, tab, map, th, ph, lane, B, found, first, mu, tmp);
-          first = false;
-          if (ok2) hi = mu; else lo = mu;
-        }
-        nug = hi + P.eps;
-#pragma unroll 1
-        for (int it = 0; it < 8 && !ok; ++it) {
-          ok = Eng::solve(P, tab, map, th, ph, lane, B, found, false, nug, o);
-          if (!ok) nug *= 2.0;
-        }
-        if (lane == 0) atomicAdd(P.counters + CNT_NUGGET_ESC, 1ull);
-      }
-      if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
-    }
-  }
+  for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb)
+    fixup_chunk<Eng, SPIN>(P, tab, map, theta, phi, n, out, var, B, ch * WAVE, lane);
 }
 
 // Main pass for 32 < n <= 16 T: one point per wave, blocked tile Cholesky.
@@ -1388,7 +195,6 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
                                                      const double *__restrict__ phi, int64_t n,
                                                      double *__restrict__ out,
                                                      double *__restrict__ var, Layout L) {
-  constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
   const double *tab = load_table(lds, P);
@@ -1396,19 +202,8 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
-  const int nrow = P.n;
-  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
-  for (int64_t pt = (int64_t)blockIdx.x * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb) {
-    const double th = theta[pt], ph = phi[pt];
-    const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
-    GroupOut o;
-    bool ok = true;
-    if (found) {
-      phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
-      ok = tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, nrow, nug, o);
-    }
-    if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
-  }
+  for (int64_t pt = (int64_t)blockIdx.x * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb)
+    point_tile<T, SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
 }
 
 // Stencil only (a2/a3): K nearest pixel indices per target.

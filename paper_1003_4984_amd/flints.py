@@ -45,9 +45,25 @@ class _Stats(ctypes.Structure):
                 ("search_failures", ctypes.c_int64), ("table_range", ctypes.c_int64)]
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("map", ctypes.c_void_p), ("theta", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("n", ctypes.c_int64), ("out", ctypes.c_void_p),
+                ("var", ctypes.c_void_p)]
+
+
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("njobs", ctypes.c_int), ("points", ctypes.c_int64), ("fused_jobs", ctypes.c_int),
+                ("classes", ctypes.c_int), ("tiles", ctypes.c_int * 4), ("tile_points", ctypes.c_int * 4),
+                ("waves_per_block", ctypes.c_int * 4), ("captured", ctypes.c_int)]
+
+
+BATCH_AUTOTUNE = 1
+
 EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
            "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
-           "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error"]
+           "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error",
+           "flints_batch_create", "flints_batch_run", "flints_batch_capture", "flints_batch_info",
+           "flints_batch_destroy"]
 
 
 def load_library(path=LIB_PATH):
@@ -82,6 +98,16 @@ def load_library(path=LIB_PATH):
     lib.flints_plan_destroy.restype = None
     lib.flints_last_error.argtypes = []
     lib.flints_last_error.restype = ctypes.c_char_p
+    lib.flints_batch_create.argtypes = [ctypes.POINTER(_Job), c_int, c_int]
+    lib.flints_batch_create.restype = vp
+    lib.flints_batch_run.argtypes = [vp, vp]
+    lib.flints_batch_run.restype = c_int
+    lib.flints_batch_capture.argtypes = [vp, vp]
+    lib.flints_batch_capture.restype = c_int
+    lib.flints_batch_info.argtypes = [vp, ctypes.POINTER(_BatchInfo)]
+    lib.flints_batch_info.restype = c_int
+    lib.flints_batch_destroy.argtypes = [vp]
+    lib.flints_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -211,3 +237,65 @@ def table_eval(plan, s, stream=None):
                                      _ptr(out, "out", torch.float64), _stream(stream))
     _check(plan._lib, rc, "flints_table_eval")
     return out
+
+
+class Batch:
+    """Many interpolation jobs in persistent fused launches (flints_batch_*).
+
+    jobs: sequence of (plan, map, theta, phi, out, var) with device tensors (var
+    may be None).  The tensors are borrowed: keep them alive while the batch is.
+    """
+
+    def __init__(self, jobs, autotune=False):
+        import torch
+        lib = load_library()
+        arr = (_Job * len(jobs))()
+        self._keep = []
+        for i, (plan, map_, theta, phi, out, var) in enumerate(jobs):
+            n = theta.numel()
+            if phi.numel() != n or out.numel() != plan.nfield * n:
+                raise FlintsError(f"job {i}: theta/phi/out sizes disagree")
+            if map_.numel() != plan.npix * plan.nfield:
+                raise FlintsError(f"job {i}: map must hold {plan.npix * plan.nfield} values")
+            if var is not None and var.numel() != plan.nfield * n:
+                raise FlintsError(f"job {i}: var has the wrong size")
+            def addr(t, name):
+                p = _ptr(t, name, torch.float64)
+                return None if p is None else p.value
+            arr[i].plan = plan.handle.value
+            arr[i].map = addr(map_, "map")
+            arr[i].theta = addr(theta, "theta")
+            arr[i].phi = addr(phi, "phi")
+            arr[i].n = n
+            arr[i].out = addr(out, "out")
+            arr[i].var = addr(var, "var")
+            self._keep.append((plan, map_, theta, phi, out, var))
+        h = lib.flints_batch_create(arr, len(jobs), BATCH_AUTOTUNE if autotune else 0)
+        if not h:
+            raise FlintsError(f"flints_batch_create failed: {_err(lib)}")
+        self._lib, self._h = lib, ctypes.c_void_p(h)
+
+    def run(self, stream=None):
+        _check(self._lib, self._lib.flints_batch_run(self._h, _stream(stream)), "flints_batch_run")
+
+    def capture(self, stream):
+        _check(self._lib, self._lib.flints_batch_capture(self._h, _stream(stream)), "flints_batch_capture")
+
+    def info(self):
+        i = _BatchInfo()
+        _check(self._lib, self._lib.flints_batch_info(self._h, ctypes.byref(i)), "flints_batch_info")
+        d = {k: getattr(i, k) for k, _ in _BatchInfo._fields_}
+        for k in ("tiles", "tile_points", "waves_per_block"):
+            d[k] = list(d[k])
+        return d
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.flints_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
