@@ -1,0 +1,273 @@
+"""Serving loop: continuous batching of lensing interpolation requests.
+
+Requests (a map set -- T, or T with Q/U -- plus displaced target directions)
+arrive over time.  The server keeps plans, and with them the device-resident
+correlation tables, in a cache keyed by (N_side, lmax, K, spin, spectrum); admits
+waiting requests first-come first-served while the HBM they need (outputs,
+variances and any new plan's table) fits a budget and a launch slot is free;
+groups the requests admitted at one step into one batched launch
+(flints_batch_*) on the next free stream, so work of different requests
+overlaps on the device; and releases a request's memory when its completion
+event has fired.  Latency is completion minus arrival; the report gives p50
+and p99 next to throughput in samples per second.
+
+The scheduling logic is independent of the device: `Server` drives an
+executor with `launch(requests, slot) -> token` and `done(token) -> bool`;
+`DeviceExecutor` is the FLINTS one.  Batching is an addition to the method; the
+paper interpolates one map at a time.
+"""
+import argparse
+import hashlib
+import json
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BYTES_PER_SAMPLE = 16          # one double of output and one of variance
+TABLE_BYTES_BOUND = 256 * 1024  # plan table upper bound used for admission
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float               # seconds on the server clock
+    nside: int
+    lmax: int
+    K: int
+    fields: str                  # "T" or "TQU"
+    n: int                       # targets
+    cl_tt: object = None
+    cl_ee: object = None
+    cl_bb: object = None
+    maps: dict = field(default_factory=dict)   # "T": tensor, "QU": tensor (device)
+    theta: object = None
+    phi: object = None
+    out: dict = field(default_factory=dict)    # filled at admission: field set -> (out, var)
+    admitted: float = None
+    finished: float = None
+
+    @property
+    def samples(self):
+        return self.n * len(self.fields)
+
+    def footprint(self, new_tables=0):
+        return self.samples * BYTES_PER_SAMPLE + new_tables * TABLE_BYTES_BOUND
+
+
+class PlanCache:
+    """Plans (and their device tables) kept across requests."""
+
+    def __init__(self, make_plan):
+        self._make = make_plan
+        self._plans = {}
+
+    @staticmethod
+    def key(nside, lmax, K, spin, cl):
+        h = hashlib.sha1(np.ascontiguousarray(cl, dtype=np.float64).tobytes()).hexdigest()
+        return (int(nside), int(lmax), int(K), int(spin), h)
+
+    def missing(self, req):
+        keys = [self.key(req.nside, req.lmax, req.K, 0, req.cl_tt)]
+        if req.fields == "TQU":
+            keys.append(self.key(req.nside, req.lmax, req.K, 2, np.concatenate([req.cl_ee, req.cl_bb])))
+        return sum(k not in self._plans for k in keys)
+
+    def get(self, nside, lmax, K, spin, cl):
+        k = self.key(nside, lmax, K, spin, cl)
+        if k not in self._plans:
+            self._plans[k] = self._make(nside, lmax, cl, K, spin)
+        return self._plans[k]
+
+    def __len__(self):
+        return len(self._plans)
+
+
+class Server:
+    """Admission by HBM footprint, FIFO, continuous batching over `slots` streams."""
+
+    def __init__(self, executor, hbm_budget, slots=2, plans=None, clock=time.perf_counter,
+                 max_group_samples=1 << 26):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_group = int(max_group_samples)   # caps one launch so groups finish in turn
+        self.slots = int(slots)
+        self.plans = plans
+        self.clock = clock
+        self.in_use = 0
+        self.peak = 0
+
+    def run(self, requests, idle=None):
+        """Serve `requests` (sorted by arrival, times relative to the start).
+        Returns the list of finished requests."""
+        t0 = self.clock()
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = deque()
+        running = {}          # slot -> (token, [requests], bytes)
+        free = list(range(self.slots))
+        done = []
+        while pending or waiting or running:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # completions
+            for slot in list(running):
+                token, reqs, nbytes = running[slot]
+                if self.ex.done(token):
+                    t = self.clock() - t0
+                    for r in reqs:
+                        r.finished = t
+                        done.append(r)
+                    self.in_use -= nbytes
+                    del running[slot]
+                    free.append(slot)
+            # admission: first come first served while memory and a slot allow
+            if free and waiting:
+                group, nbytes, nsamp = [], 0, 0
+                while waiting:
+                    r = waiting[0]
+                    if group and nsamp + r.samples > self.max_group:
+                        break
+                    need = r.footprint(self.plans.missing(r) if self.plans is not None else 0)
+                    if need > self.budget:
+                        raise ValueError(f"request {r.rid} needs {need} B, more than the budget")
+                    if self.in_use + nbytes + need > self.budget:
+                        break
+                    group.append(waiting.popleft())
+                    nbytes += need
+                    nsamp += r.samples
+                if group:
+                    slot = free.pop(0)
+                    t = self.clock() - t0
+                    for r in group:
+                        r.admitted = t
+                    token = self.ex.launch(group, slot)
+                    running[slot] = (token, group, nbytes)
+                    self.in_use += nbytes
+                    self.peak = max(self.peak, self.in_use)
+                    continue
+            if idle is not None:
+                idle()
+        return done
+
+
+def report(done, wall):
+    lat = np.array([r.finished - r.arrival for r in done])
+    samples = sum(r.samples for r in done)
+    return {"requests": len(done), "samples": int(samples), "wall_s": wall,
+            "samples_per_s": samples / wall if wall > 0 else None,
+            "latency_p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "latency_p99_s": float(np.percentile(lat, 99)) if len(lat) else None}
+
+
+class DeviceExecutor:
+    """FLINTS executor: one flints batch per admitted group, on `slots` streams
+    of default priority; completion via a recorded event."""
+
+    def __init__(self, plans, slots):
+        import torch
+        import paper_1003_4984_amd as fl
+        self.fl, self.torch = fl, torch
+        self.plans = plans
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+
+    def jobs_for(self, r):
+        torch, fl = self.torch, self.fl
+        jobs = []
+        p0 = self.plans.get(r.nside, r.lmax, r.K, 0, r.cl_tt)
+        o = torch.empty(r.n, dtype=torch.float64, device=r.theta.device)
+        v = torch.empty(r.n, dtype=torch.float64, device=r.theta.device)
+        r.out["T"] = (o, v)
+        jobs.append((p0, r.maps["T"], r.theta, r.phi, o, v))
+        if r.fields == "TQU":
+            p2 = self.plans.get(r.nside, r.lmax, r.K, 2, np.concatenate([r.cl_ee, r.cl_bb]))
+            o2 = torch.empty(2 * r.n, dtype=torch.float64, device=r.theta.device)
+            v2 = torch.empty(2 * r.n, dtype=torch.float64, device=r.theta.device)
+            r.out["QU"] = (o2, v2)
+            jobs.append((p2, r.maps["QU"], r.theta, r.phi, o2, v2))
+        return jobs
+
+    def launch(self, group, slot):
+        torch = self.torch
+        s = self.streams[slot]
+        jobs = [j for r in group for j in self.jobs_for(r)]
+        # inputs were written on the default stream; order this stream after it
+        s.wait_stream(torch.cuda.current_stream())
+        b = self.fl.Batch(jobs)
+        b.run(s)
+        ev = torch.cuda.Event()
+        ev.record(s)
+        return (ev, b, jobs)
+
+    def done(self, token):
+        ev, b, jobs = token
+        if ev.query():
+            b.close()
+            return True
+        return False
+
+
+def make_requests(n_req, rate, seed=0, nsides=(256, 1024, 2048, 4096), weights=(0.4, 0.3, 0.2, 0.1),
+                  tqu_frac=0.5, K=32, device="cuda", max_points=None):
+    """Poisson stream of lensing requests (rate per second) with fresh seeded
+    maps and deflections, lmax = N_side; inputs are synthesised before the
+    clock starts."""
+    import torch
+    from workload import configs, spectra
+    from workload.seeds import rng as seeded
+    g = seeded(5, seed, 0)
+    t, reqs = 0.0, []
+    p = np.asarray(weights, dtype=np.float64)
+    for i in range(n_req):
+        t += g.exponential(1.0 / rate)
+        nside = int(g.choice(nsides, p=p / p.sum()))
+        lmax = nside
+        fields = "TQU" if g.uniform() < tqu_frac else "T"
+        tt, ee, te, bb = spectra.cl_acoustic(lmax)
+        job = seed * 100000 + i
+        m = configs.maps(5, nside, lmax, fields, device, job=job)
+        maps = {"T": m["T"]}
+        if fields == "TQU":
+            maps["QU"] = torch.cat([m["Q"], m["U"]])
+        th, ph = configs.lensing_targets(5, nside, lmax, device, job=job)
+        if max_points is not None and th.numel() > max_points:
+            th, ph = th[:max_points].contiguous(), ph[:max_points].contiguous()
+        reqs.append(Request(rid=i, arrival=t, nside=nside, lmax=lmax, K=K, fields=fields, n=th.numel(),
+                            cl_tt=tt, cl_ee=ee, cl_bb=bb, maps=maps, theta=th, phi=ph))
+    return reqs
+
+
+def main():
+    ap = argparse.ArgumentParser(description="FLINTS serving simulation (Poisson request stream)")
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--rate", type=float, default=20.0, help="requests per second")
+    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--group-msamples", type=float, default=64.0, help="samples per launch cap (millions)")
+    ap.add_argument("--nsides", default="256,1024,2048")
+    ap.add_argument("--weights", default="0.4,0.3,0.2")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    import paper_1003_4984_amd as fl
+    nsides = tuple(int(x) for x in args.nsides.split(","))
+    weights = tuple(float(x) for x in args.weights.split(","))
+    reqs = make_requests(args.requests, args.rate, args.seed, nsides, weights)
+    torch.cuda.synchronize()
+    plans = PlanCache(lambda nside, lmax, cl, K, spin: fl.Plan(nside, lmax, cl, K, spin))
+    ex = DeviceExecutor(plans, args.slots)
+    srv = Server(ex, args.budget_gb * 2 ** 30, args.slots, plans,
+                 max_group_samples=int(args.group_msamples * 1e6))
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    rep = report(done, time.perf_counter() - t0)
+    rep.update({"rate_per_s": args.rate, "slots": args.slots, "plans_cached": len(plans),
+                "group_msamples": args.group_msamples,
+                "peak_admitted_bytes": srv.peak, "nsides": list(nsides), "K": 32})
+    print(json.dumps(rep), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,120 @@
+"""Serving loop scheduling (CPU, fake executor on a virtual clock): FIFO
+admission by HBM footprint, launch-slot limits, continuous batching of requests
+that arrive while slots are busy, plan-table accounting, latency report."""
+import numpy as np
+import pytest
+
+from paper_1003_4984_amd.serve import Request, Server, PlanCache, report, BYTES_PER_SAMPLE, TABLE_BYTES_BOUND
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor:
+    """Completes a group after 1 ms per 1000 samples; records concurrency."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.live = {}
+        self.max_live = 0
+        self.groups = []
+
+    def launch(self, group, slot):
+        assert slot not in self.live
+        dur = 1e-3 * sum(r.samples for r in group) / 1000.0
+        self.live[slot] = self.clock() + dur
+        self.max_live = max(self.max_live, len(self.live))
+        self.groups.append([r.rid for r in group])
+        return (slot, self.clock() + dur)
+
+    def done(self, token):
+        slot, t_end = token
+        if self.clock() >= t_end:
+            self.live.pop(slot, None)
+            return True
+        return False
+
+
+def _reqs(arrivals, ns, fields="T"):
+    return [Request(rid=i, arrival=a, nside=16, lmax=16, K=8, fields=fields, n=n,
+                    cl_tt=np.ones(17)) for i, (a, n) in enumerate(zip(arrivals, ns))]
+
+
+def _serve(reqs, budget, slots, plans=None):
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    srv = Server(ex, budget, slots, plans, clock=clock)
+
+    def idle():
+        clock.t += 1e-4
+    done = srv.run(reqs, idle=idle)
+    return srv, ex, done, clock
+
+
+def test_all_served_fifo_and_latency():
+    reqs = _reqs([0.0, 0.001, 0.002, 0.010, 0.011], [2000, 3000, 1000, 4000, 500])
+    srv, ex, done, clock = _serve(reqs, budget=10 ** 9, slots=2)
+    assert sorted(r.rid for r in done) == list(range(5))
+    adm = [r.admitted for r in sorted(done, key=lambda r: r.rid)]
+    assert all(a <= b for a, b in zip(adm, adm[1:]))          # first come first admitted
+    for r in done:
+        assert r.arrival <= r.admitted <= r.finished
+    rep = report(done, clock.t)
+    assert rep["requests"] == 5 and rep["samples"] == sum(r.samples for r in reqs)
+    assert rep["latency_p50_s"] <= rep["latency_p99_s"]
+
+
+def test_budget_and_slots_respected():
+    ns = [5000] * 12
+    reqs = _reqs(np.linspace(0, 0.002, 12), ns)
+    budget = 2 * 5000 * BYTES_PER_SAMPLE          # two requests in flight at most
+    srv, ex, done, _ = _serve(reqs, budget=budget, slots=3)
+    assert len(done) == 12
+    assert srv.peak <= budget
+    assert ex.max_live <= 3
+
+
+def test_continuous_batching_groups_waiting_requests():
+    # one long request holds the only slot; the ones arriving meanwhile are
+    # admitted together when it completes
+    reqs = _reqs([0.0, 0.0005, 0.0006, 0.0007], [50000, 100, 100, 100])
+    srv, ex, done, _ = _serve(reqs, budget=10 ** 9, slots=1)
+    assert ex.groups[0] == [0]
+    assert ex.groups[1] == [1, 2, 3]
+
+
+def test_request_over_budget_rejected():
+    reqs = _reqs([0.0], [10 ** 6])
+    with pytest.raises(ValueError):
+        _serve(reqs, budget=1000, slots=1)
+
+
+def test_new_plan_tables_count_against_budget():
+    made = []
+    plans = PlanCache(lambda *a: made.append(a) or object())
+    r = _reqs([0.0], [100], fields="TQU")[0]
+    r.cl_ee, r.cl_bb = np.ones(17), np.zeros(17)
+    assert plans.missing(r) == 2
+    assert r.footprint(plans.missing(r)) == 3 * 100 * BYTES_PER_SAMPLE + 2 * TABLE_BYTES_BOUND
+    plans.get(16, 16, 8, 0, r.cl_tt)
+    assert plans.missing(r) == 1 and len(plans) == 1
+    plans.get(16, 16, 8, 0, r.cl_tt)
+    assert len(made) == 1
+
+
+def test_group_cap_splits_launches():
+    reqs = _reqs([0.0, 0.0001, 0.0002, 0.0003], [50000, 3000, 3000, 3000])
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    srv = Server(ex, 10 ** 9, 1, None, clock=clock, max_group_samples=5000)
+
+    def idle():
+        clock.t += 1e-4
+    done = srv.run(reqs, idle=idle)
+    assert len(done) == 4
+    assert ex.groups == [[0], [1], [2], [3]]
