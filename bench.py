@@ -201,7 +201,7 @@ def main():
         "kernel_s": {"spin0": float(t_spin0.mean()), "spin2": float(t_spin2.mean())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "spin-2 interpolation launch (k_interp64<64,64,2> + escalation scan)",
+                     "kernel": "spin-2 interpolation launch (k_interp_tile<4,2> + fix-up scan)",
                      "flops_per_point": flops_spin2(K)},
         "stats": {"spin0": st0, "spin2": st2},
     }

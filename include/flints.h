@@ -174,9 +174,9 @@ void flints_plan_destroy(flints_plan_t plan);
 /*
  * Batched execution: many interpolation jobs (different plans -- N_side, K,
  * spin -- and target counts) in persistent fused launches.  Jobs are cut into
- * tiles of consecutive targets; FP64 jobs (FLINTS_VAR_PAPER) of one system-size
- * class (n <= 16, <= 32, <= 48, <= 64 rows, n = K or 2K) share one persistent
- * launch whose blocks take tiles from a device queue, reload the job's
+ * tiles of consecutive targets; FP64 jobs (FLINTS_VAR_PAPER) of one launch group
+ * (system size n <= 16, <= 32, <= 48, <= 64 rows, n = K or 2K, and table size)
+ * share one persistent launch whose blocks take tiles from a device queue, reload the job's
  * correlation table into LDS when the job changes, and run the same per-point
  * arithmetic as flints_interpolate (results are bit-identical to it); spin 0
  * and spin 2 jobs mix freely within a class.  Jobs with FP32_IR or MSE-variance
@@ -221,10 +221,12 @@ typedef struct {
   int njobs;
   int64_t points;            /* total targets */
   int fused_jobs;            /* jobs on the persistent launches */
-  int classes;               /* persistent launches per run */
-  int tiles[4];              /* tiles per class (n <= 16, 32, 48, 64) */
-  int tile_points[4];        /* targets per tile per class (0 = class unused) */
-  int waves_per_block[4];
+  int classes;               /* persistent launch groups used per run */
+  /* per launch group g = 3 * engine + bucket: engine by rows n <= 16, 32, 48,
+   * 64; bucket by correlation-table size <= 16 KB, <= 48 KB, larger */
+  int tiles[12];
+  int tile_points[12];       /* targets per tile (0 = group unused) */
+  int waves_per_block[12];
   int captured;              /* 1 if runs replay a graph */
 } flints_batch_info_t;
 

@@ -33,7 +33,9 @@ struct BatchTile {
   int64_t start, count;
 };
 
-constexpr int NCLASS = 4;   // row group NT = 1, 2; tile T = 3, 4
+constexpr int NENGINE = 4;   // row group NT = 1, 2; tile T = 3, 4
+constexpr int NTABB = 3;     // table-size buckets: <= 16 KB, <= 48 KB, larger
+constexpr int NCLASS = NENGINE * NTABB;   // launch groups, index NTABB * engine + bucket
 
 __global__ void k_batch_reset(unsigned *ctr, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,10 +134,16 @@ struct Batch {
   int64_t points = 0;
 };
 
+// Launch group of a job: engine by system size, and table-size bucket, so a
+// large table (few waves fit beside it in LDS) does not set the occupancy of
+// jobs with small ones.
 static int job_class(const Plan *p) {
   if (p->d.precision != FLINTS_FP64 || p->d.var_kind != FLINTS_VAR_PAPER) return -1;
   const int n = p->d.n;
-  return n <= 16 ? 0 : n <= 32 ? 1 : n <= 48 ? 2 : 3;
+  const int e = n <= 16 ? 0 : n <= 32 ? 1 : n <= 48 ? 2 : 3;
+  const int tb = p->d.ntab * p->d.nfun * 8;
+  const int k = tb <= (16 << 10) ? 0 : tb <= (48 << 10) ? 1 : 2;
+  return NTABB * e + k;
 }
 
 template <int CLS, bool FIX>
@@ -144,7 +152,7 @@ static const void *batch_kernel() {
 }
 
 static const void *class_kernel(int c, bool fix) {
-  switch (c) {
+  switch (c / NTABB) {
     case 0: return fix ? batch_kernel<0, true>() : batch_kernel<0, false>();
     case 1: return fix ? batch_kernel<1, true>() : batch_kernel<1, false>();
     case 2: return fix ? batch_kernel<2, true>() : batch_kernel<2, false>();
@@ -156,7 +164,7 @@ static void launch_class(int c, bool fix, int blocks, int wpb, int lds, hipStrea
                          const BatchJob *jobs, const BatchTile *tiles, int ntiles, unsigned *ctr,
                          const Layout &L) {
   const dim3 g((unsigned)blocks), b((unsigned)(wpb * WAVE));
-  switch (c) {
+  switch (c / NTABB) {
     case 0:
       if (fix) hipLaunchKernelGGL((k_batch<0, true>), g, b, lds, s, jobs, tiles, ntiles, ctr, L);
       else hipLaunchKernelGGL((k_batch<0, false>), g, b, lds, s, jobs, tiles, ntiles, ctr, L);
@@ -197,8 +205,9 @@ static std::vector<BatchTile> make_tiles(const Batch &b, int c, int tile_pts, in
 
 // LDS layout and the waves-per-block choice (most waves per CU) for class c.
 static int size_class(ClassRun &r, int c, int wpb_cap) {
-  const int ppw = c < 2 ? 4 : 1;
-  const int min_mat = c < 2 ? 0 : c * TILE_D;   // tile path T = c + 1 stages T - 1 tiles
+  const int e = c / NTABB;
+  const int ppw = e < 2 ? 4 : 1;
+  const int min_mat = e < 2 ? 0 : e * TILE_D;   // tile path T = e + 1 stages T - 1 tiles
   r.L = make_layout(r.max_tab, 1, r.max_K, r.max_n, ppw, 1, 3, min_mat);
   int lds_max = 0, ncu = 0, dev = 0;
   hipGetDevice(&dev);

@@ -74,7 +74,8 @@ def test_batch_equals_single(gpu_ok):
     ref = _single(jobs)
     b = fl.Batch(jobs)
     info = b.info()
-    assert info["njobs"] == len(JOBS) and info["classes"] == 4
+    assert info["njobs"] == len(JOBS) and info["classes"] >= 4
+    assert all((t > 0) == (w > 0) for t, w in zip(info["tiles"], info["waves_per_block"]))
     assert info["fused_jobs"] == sum(1 for j in JOBS if j[3] == fl.FP64 and j[4] == fl.VAR_PAPER and j[5] > 0)
     b.run()
     torch.cuda.synchronize()
@@ -113,9 +114,10 @@ def test_batch_autotune(gpu_ok):
     ref = _single(jobs)
     b = fl.Batch(jobs, autotune=True)
     info = b.info()
-    for c in range(4):
-        assert info["tile_points"][c] in (256, 1024, 4096, 16384)
-        assert 1 <= info["waves_per_block"][c] <= 8
+    for c in range(12):
+        if info["tiles"][c]:
+            assert info["tile_points"][c] in (256, 1024, 4096, 16384)
+            assert 1 <= info["waves_per_block"][c] <= 8
     for *_, out, var in jobs:
         out.fill_(0.0)
         var.fill_(0.0)
