@@ -122,6 +122,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32ir"])
     ap.add_argument("--cpu-sample", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before timing, copy this many MiB device to device once (a plain copy of "
+                         "known size that calibrates HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,6 +138,13 @@ def main():
     torch.cuda.set_device(0)
     inp = make_inputs(shape, dev)
     n = inp["theta"].numel()
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
+        del src, dst
     prec = fl.FP64 if args.precision == "fp64" else fl.FP32_IR
     log("building plans")
     p0 = fl.Plan(shape["nside"], shape["lmax"], inp["tt"], shape["K"], 0, precision=prec)

@@ -158,6 +158,18 @@ inline Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int
   return L;
 }
 
+// Block index with the grid regrouped by XCD.  The dispatcher hands blocks to
+// the 8 XCDs of an MI355X round robin (block b runs on XCD b mod 8), and each
+// XCD has its own L2; numbering the blocks of one XCD consecutively makes the
+// targets it works on at any moment one contiguous RING range, so the map lines
+// their stencils share are fetched into one L2 instead of eight.
+constexpr int NXCD = 8;
+__device__ inline int64_t xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  if (nb % NXCD) return b;
+  return (int64_t)(b % NXCD) * (nb / NXCD) + b / NXCD;
+}
+
 __device__ inline void count_event(unsigned long long *ctr, bool cond, int lane) {
   unsigned long long m = __ballot(cond);
   if (m && lane == 0) atomicAdd(ctr, (unsigned long long)__popcll(m));

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp64(PlanDev P, const do
   const int row = lane % G;
   const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
 
-  for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb) {
+  for (int64_t g = xcd_block() * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb) {
     unsigned act_mask = 0;
 #pragma unroll 1
     for (int q = 0; q < PPW; ++q) {
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate(PlanDev P, const do
   const int row = lane % G;
   const double nug0 = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
   const int64_t nchunks = (n + WAVE - 1) / WAVE;
-  for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb) {
+  for (int64_t ch = xcd_block() * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb) {
     const int64_t p0 = ch * WAVE + lane;
     const unsigned long long bits =
         p0 < n ? (unsigned long long)__double_as_longlong(out[p0]) : 0ull;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs(PlanDev P, const d
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
   const int64_t ngroups = (n + 3) / 4;
-  for (int64_t g = (int64_t)blockIdx.x * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb)
+  for (int64_t g = xcd_block() * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb)
     group_rs<NT, SPIN>(P, tab, map, theta, phi, n, out, var, B, g * 4, lane);
 }
 
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_fixup(PlanDev P, const doubl
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
   const int64_t nchunks = (n + WAVE - 1) / WAVE;
-  for (int64_t ch = (int64_t)blockIdx.x * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb)
+  for (int64_t ch = xcd_block() * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb)
     fixup_chunk<Eng, SPIN>(P, tab, map, theta, phi, n, out, var, B, ch * WAVE, lane);
 }
 
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
-  for (int64_t pt = (int64_t)blockIdx.x * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb)
+  for (int64_t pt = xcd_block() * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb)
     point_tile<T, SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
 }
 
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(STENCIL_WPB * WAVE) void k_stencil(PlanDev P, const
   RingSpan *rs = (RingSpan *)(wb + L.off_rings);
   int *sel = (int *)(wb + L.off_sel);
   const int K = P.K;
-  for (int64_t pt = (int64_t)blockIdx.x * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb) {
+  for (int64_t pt = xcd_block() * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb) {
     const double th = theta[pt], ph = phi[pt];
     const bool good = (th >= 0.0) && (th <= kconst(PI_D)) && isfinite(ph);
     bool found = false;
