@@ -44,6 +44,38 @@ def flops_spin2(K):
     return 16.0 / 3.0 * K ** 3 + 16 * K ** 2 + 60 * (K * (K + 1) / 2 + K)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interp_tile_nside4096_K32.md")
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1003_4984_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the spin-2 kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if that summary
+    is for other kernel sources or another workload."""
+    if workload != "nside4096" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -210,7 +242,9 @@ def main():
                       "note": "per full-sky request (T then Q/U launch), HIP events"},
         "kernel_s": {"spin0": float(t_spin0.mean()), "spin2": float(t_spin2.mean())},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(args.workload),
+                     "traffic_unit": "HBM bytes per spin-2 launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "kernel": "spin-2 interpolation launch (k_interp_tile<4,2> + fix-up scan)",
                      "flops_per_point": flops_spin2(K)},
         "stats": {"spin0": st0, "spin2": st2},
