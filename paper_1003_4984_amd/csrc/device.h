@@ -128,6 +128,9 @@ struct Layout {
   int matsz;
 };
 
+// Words between fields of the neighbour records (field-major, K + 1 records).
+__host__ __device__ inline int nb_stride(int K) { return (K + 2) & ~1; }
+
 inline int al16(int x) { return (x + 15) & ~15; }
 
 // Per-wave LDS: the stencils of the wave's points, then a region used first by
@@ -148,7 +151,7 @@ inline Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int
   L.off_rings = s; s = al16(s + WAVE * (int)sizeof(RingSpan));
   // assembly view
   int a = u0;
-  L.off_nb = a;    a = al16(a + (K + 1) * NBF * 8);
+  L.off_nb = a;    a = al16(a + nb_stride(K) * NBF * 8);
   L.matsz = std::max(n * (n + 1) / 2, min_mat);
   L.off_mat = a;   a = al16(a + nsys * L.matsz * 8);
   L.off_rhs = a;   a = al16(a + nsys * n * NR * 8);
@@ -326,6 +329,12 @@ __device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, dou
 }
 
 // ---------------------------------------------------------------- a4/a5 records
+// Neighbour records, field-major (record a's field f at nb[f * nbs + a], nbs =
+// nb_stride(K)) so that lanes reading the records of consecutive neighbours
+// read consecutive words.  Record 0 is the target.  Fields: chord offset from
+// the target in the target's (e_theta, e_phi, z) frame (0-2), the point's own
+// e_theta (3-5) and e_phi (6-7) in that frame, gathered map values (8-9).
+
 template <int SPIN>
 __device__ void neighbour_records(const PlanDev &P, double th, double ph, int lane, const int *sel,
                                   double *nb, const double *__restrict__ map) {
@@ -334,13 +343,14 @@ __device__ void neighbour_records(const PlanDev &P, double th, double ph, int la
   const double twopi = kconst(TWO_PI_D);
   const double phr = ph - twopi * floor(ph / twopi);
   const int K = P.K;
+  const int ns = nb_stride(K);
   for (int a = lane; a <= K; a += WAVE) {
-    double *rec = nb + a * NBF;
+    double f[NBF];
     if (a == 0) {
-      rec[0] = 0.0; rec[1] = 0.0; rec[2] = 0.0;
-      rec[3] = zt;  rec[4] = 0.0; rec[5] = -st;
-      rec[6] = 0.0; rec[7] = 1.0;
-      rec[8] = 0.0; rec[9] = 0.0;
+      f[0] = 0.0; f[1] = 0.0; f[2] = 0.0;
+      f[3] = zt;  f[4] = 0.0; f[5] = -st;
+      f[6] = 0.0; f[7] = 1.0;
+      f[8] = 0.0; f[9] = 0.0;
     } else {
       const int64_t p = sel[a - 1];
       const Ring R = ring_geom(P.nside, pix_ring(P.nside, p));
@@ -349,97 +359,121 @@ __device__ void neighbour_records(const PlanDev &P, double th, double ph, int la
       sincos_bounded(0.5 * dphi, sh, ch);
       const double sd = 2.0 * sh * ch, cd = 1.0 - 2.0 * sh * sh;
       const double sdiff = (zt - R.z) * (zt + R.z) / (R.s + st);
-      rec[0] = sdiff - 2.0 * R.s * sh * sh;
-      rec[1] = R.s * sd;
-      rec[2] = R.z - zt;
-      rec[3] = R.z * cd; rec[4] = R.z * sd; rec[5] = -R.s;
-      rec[6] = -sd;      rec[7] = cd;
-      rec[8] = map[p];
-      rec[9] = (SPIN == 2) ? map[P.npix + p] : 0.0;
+      f[0] = sdiff - 2.0 * R.s * sh * sh;
+      f[1] = R.s * sd;
+      f[2] = R.z - zt;
+      f[3] = R.z * cd; f[4] = R.z * sd; f[5] = -R.s;
+      f[6] = -sd;      f[7] = cd;
+      f[8] = map[p];
+      f[9] = (SPIN == 2) ? map[P.npix + p] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < NBF; ++i) nb[i * ns + a] = f[i];
   }
 }
 
 // ---------------------------------------------------------------- a6 assembly
+// 1 / d to full precision: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
+// Covariance entries of the pair (a, b) from their records.  Spin 0: c[0] =
+// zeta(beta_ab) / zeta(0).  Spin 2: the 2 x 2 block Cov(Q_a, Q_b), Cov(Q_a, U_b),
+// Cov(U_a, Q_b), Cov(U_a, U_b) from <P_a P_b*> = xi+ e^{2i(psi_ab - psi_ba)} and
+// <P_a P_b> = xi- e^{2i(psi_ab + psi_ba)}, the bearings psi taken from the chord
+// projected on each point's (e_theta, e_phi).  Returns false if the distance is
+// beyond the table.
+template <int SPIN>
+__device__ __forceinline__ bool pair_cov(const PlanDev &P, const double *tab, const double *nb, int ns,
+                                         int a, int b, bool paper, double (&c)[4]) {
+  const double dx = nb[a] - nb[b], dy = nb[ns + a] - nb[ns + b], dz = nb[2 * ns + a] - nb[2 * ns + b];
+  const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+  if (SPIN == 0) {
+    double f;
+    const bool in = table_lookup(tab, P.ntab, 1, P.inv_h, s, &f);
+    c[0] = f;
+    return in;
+  }
+  double f[2];
+  const bool in = table_lookup(tab, P.ntab, 2, P.inv_h, s, f);
+  const double xa = dx * nb[3 * ns + a] + dy * nb[4 * ns + a] + dz * nb[5 * ns + a];
+  const double ya = dx * nb[6 * ns + a] + dy * nb[7 * ns + a];
+  const double xb = dx * nb[3 * ns + b] + dy * nb[4 * ns + b] + dz * nb[5 * ns + b];
+  const double yb = dx * nb[6 * ns + b] + dy * nb[7 * ns + b];
+  const double na = xa * xa + ya * ya, nbn = xb * xb + yb * yb;
+  // the projections vanish together only for coincident points (beta = 0),
+  // where the bearings are undefined and both phases are taken as 1
+  const double prod = na * nbn;
+  const bool sep = prod > 0.0;
+  const double inv = recip(sep ? prod : 1.0);
+  const double ia = nbn * inv, ib = na * inv;
+  const double ca = sep ? (xa * xa - ya * ya) * ia : 1.0, sa = sep ? 2.0 * xa * ya * ia : 0.0;
+  const double cb = sep ? (xb * xb - yb * yb) * ib : 1.0, sb = sep ? 2.0 * xb * yb * ib : 0.0;
+  const double gr = f[0] * (ca * cb + sa * sb), gi = f[0] * (sa * cb - ca * sb);
+  const double pr = paper ? 0.0 : f[1] * (ca * cb - sa * sb);
+  const double pim = paper ? 0.0 : f[1] * (sa * cb + ca * sb);
+  c[0] = gr + pr;   // QQ
+  c[1] = pim - gi;  // QU
+  c[2] = pim + gi;  // UQ
+  c[3] = gr - pr;   // UU
+  return in;
+}
+
+// Packed lower triangle of S (row-major, unit diagonal before the nugget) and
+// the right-hand sides [b | data] (spin 0) or [b_Q | b_U | data] (spin 2) in
+// LDS.  First pass: one neighbour per lane, its target covariances, data and
+// diagonal; second pass: the off-diagonal pairs (a, b), 1 <= b < a <= K, with no
+// per-pair branches.
 template <int SPIN, int NR>
 __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, int lane,
                          double *mat, double *rhs) {
   const int K = P.K;
-  const int npairs = (K + 1) * (K + 2) / 2;
+  const int ns = nb_stride(K);
   const bool paper = (P.mode == FLINTS_S2_PAPER);
   bool range_bad = false;
-  // pair q = a (a + 1) / 2 + b, 0 <= b <= a <= K; lanes stride by WAVE through q
-  int a = 0, b = lane;
-  while (b > a) { b -= a + 1; ++a; }
+  for (int a = 1 + lane; a <= K; a += WAVE) {
+    double c[4];
+    range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, 0, paper, c);
+    if (SPIN == 0) {
+      const int ra = a - 1;
+      mat[tri(ra) + ra] = 1.0;
+      rhs[ra * NR + 0] = c[0];
+      rhs[ra * NR + 1] = nb[8 * ns + a];
+    } else {
+      const int ra = 2 * (a - 1);
+      mat[tri(ra) + ra] = 1.0;
+      mat[tri(ra + 1) + ra] = 0.0;
+      mat[tri(ra + 1) + ra + 1] = 1.0;
+      rhs[ra * NR + 0] = c[0];          // Cov(Q_a, Q_0)
+      rhs[ra * NR + 1] = c[1];          // Cov(Q_a, U_0)
+      rhs[(ra + 1) * NR + 0] = c[2];    // Cov(U_a, Q_0)
+      rhs[(ra + 1) * NR + 1] = c[3];    // Cov(U_a, U_0)
+      rhs[ra * NR + 2] = nb[8 * ns + a];
+      rhs[(ra + 1) * NR + 2] = nb[9 * ns + a];
+    }
+  }
+  // off-diagonal pair q = (a - 1)(a - 2) / 2 + (b - 1); lanes stride by WAVE
+  const int npairs = K * (K - 1) / 2;
+  int a = 2, b = 1 + lane;
+  while (b >= a) { b -= a - 1; ++a; }
   for (int q = lane; q < npairs; q += WAVE) {
-    if (q > 0) {
-      const double *A = nb + a * NBF;
-      const double *B = nb + b * NBF;
-      if (SPIN == 0) {
-        const int ra = a - 1;
-        if (a == b) {
-          mat[tri(ra) + ra] = 1.0;
-          rhs[ra * NR + 1] = A[8];
-        } else {
-          const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
-          const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
-          double f;
-          range_bad |= !table_lookup(tab, P.ntab, 1, P.inv_h, s, &f);
-          if (b == 0) rhs[ra * NR + 0] = f;
-          else mat[tri(ra) + (b - 1)] = f;
-        }
-      } else {
-        const int ra = 2 * (a - 1);
-        if (a == b) {
-          mat[tri(ra) + ra] = 1.0;
-          mat[tri(ra + 1) + ra] = 0.0;
-          mat[tri(ra + 1) + ra + 1] = 1.0;
-          rhs[ra * NR + 2] = A[8];
-          rhs[(ra + 1) * NR + 2] = A[9];
-        } else {
-          const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
-          const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
-          double f[2];
-          range_bad |= !table_lookup(tab, P.ntab, 2, P.inv_h, s, f);
-          // bearings: e^{2 i psi} from the chord projected on each point's (e_theta, e_phi)
-          const double xa = dx * A[3] + dy * A[4] + dz * A[5];
-          const double ya = dx * A[6] + dy * A[7];
-          const double xb = dx * B[3] + dy * B[4] + dz * B[5];
-          const double yb = dx * B[6] + dy * B[7];
-          const double na = xa * xa + ya * ya, nbn = xb * xb + yb * yb;
-          const double prod = na * nbn;
-          double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
-          if (prod > 0.0) {
-            const double inv = 1.0 / prod;
-            const double ia = nbn * inv, ib = na * inv;
-            ca = (xa * xa - ya * ya) * ia; sa = 2.0 * xa * ya * ia;
-            cb = (xb * xb - yb * yb) * ib; sb = 2.0 * xb * yb * ib;
-          } else {
-            if (na > 0.0) { const double in = 1.0 / na; ca = (xa * xa - ya * ya) * in; sa = 2.0 * xa * ya * in; }
-            if (nbn > 0.0) { const double in = 1.0 / nbn; cb = (xb * xb - yb * yb) * in; sb = 2.0 * xb * yb * in; }
-          }
-          // <P_a P_b*> = xi+ e^{2i(psi_ab - psi_ba)},  <P_a P_b> = xi- e^{2i(psi_ab + psi_ba)}
-          const double gr = f[0] * (ca * cb + sa * sb), gi = f[0] * (sa * cb - ca * sb);
-          const double pr = paper ? 0.0 : f[1] * (ca * cb - sa * sb);
-          const double pim = paper ? 0.0 : f[1] * (sa * cb + ca * sb);
-          const double QQ = gr + pr, UU = gr - pr, QU = pim - gi, UQ = pim + gi;
-          if (b == 0) {
-            rhs[ra * NR + 0] = QQ;        // Cov(Q_a, Q_0)
-            rhs[(ra + 1) * NR + 0] = UQ;  // Cov(U_a, Q_0)
-            rhs[ra * NR + 1] = QU;        // Cov(Q_a, U_0)
-            rhs[(ra + 1) * NR + 1] = UU;  // Cov(U_a, U_0)
-          } else {
-            const int rb = 2 * (b - 1);
-            mat[tri(ra) + rb] = QQ;
-            mat[tri(ra) + rb + 1] = QU;
-            mat[tri(ra + 1) + rb] = UQ;
-            mat[tri(ra + 1) + rb + 1] = UU;
-          }
-        }
-      }
+    double c[4];
+    range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, b, paper, c);
+    if (SPIN == 0) {
+      mat[tri(a - 1) + (b - 1)] = c[0];
+    } else {
+      const int ra = 2 * (a - 1), rb = 2 * (b - 1);
+      mat[tri(ra) + rb] = c[0];
+      mat[tri(ra) + rb + 1] = c[1];
+      mat[tri(ra + 1) + rb] = c[2];
+      mat[tri(ra + 1) + rb + 1] = c[3];
     }
     b += WAVE;
-    while (b > a) { b -= a + 1; ++a; }
+    while (b >= a) { b -= a - 1; ++a; }
   }
   count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
 }
@@ -707,14 +741,6 @@ __device__ __forceinline__ void rowsys_load(RowSys<NT, NR> &S, const double *mat
 #pragma unroll
     for (int q = 0; q < NR; ++q) S.r[t][q] = real ? rhs[ic * NR + q] : 0.0;
   }
-}
-
-// 1 / d to full precision: the hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double recip(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  r = fma(r, fma(-d, r, 1.0), r);
-  return r;
 }
 
 // Step K of the row-group elimination.  d = a_KK and inv = 1 / d arrive from
