@@ -113,15 +113,17 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
   d.pivot_ratio_min = o.pivot_ratio_min > 0.0 ? o.pivot_ratio_min : 1e-3;
   d.refine_tol = o.refine_tol > 0.0 ? o.refine_tol : 1e-3;
   // Search radii from the expected pixel count in a cap: N(r) = 6 nside^2 (1 - cos r).
-  // r0 holds ~2K pixels on average, rcap ~5K; the table covers pair separations up
-  // to 2 rcap, i.e. s = sin(beta/2) <= sin(rcap).
+  // r0 holds max(1.3K, K + 8) pixel centres on average (pixel counts in a disc
+  // vary little on the HEALPix lattice, so the first disc nearly always holds K
+  // and its candidates fit one pass of a wavefront); rcap ~5K; the table covers
+  // pair separations up to 2 rcap, i.e. s = sin(beta/2) <= sin(rcap).
   const double n2 = (double)nside * (double)nside;
   auto cap_radius = [&](double count) {
     double c = 1.0 - count / (6.0 * n2);
     if (c <= -1.0) return 3.14159265358979323846;
     return std::acos(c);
   };
-  d.r0 = cap_radius(2.0 * K);
+  d.r0 = cap_radius(std::max(1.3 * K, K + 8.0));
   d.rcap = std::max(d.r0, cap_radius(5.0 * K + 8.0));
   d.smax = d.rcap >= 0.5 * 3.14159265358979323846 ? 1.0 : std::min(1.0, std::sin(d.rcap) * 1.0001);
 
