@@ -207,7 +207,7 @@ static std::vector<BatchTile> make_tiles(const Batch &b, int c, int tile_pts, in
 static int size_class(ClassRun &r, int c, int wpb_cap) {
   const int e = c / NTABB;
   const int ppw = e < 2 ? 4 : 1;
-  const int min_mat = e < 2 ? 0 : e * TILE_D;   // tile path T = e + 1 stages T - 1 tiles
+  const int min_mat = e < 2 ? 0 : e * TILE_D + 16;   // tile path T = e + 1: T - 1 staged tiles + pivots
   r.L = make_layout(r.max_tab, 1, r.max_K, r.max_n, ppw, 1, 3, min_mat);
   int lds_max = 0, ncu = 0, dev = 0;
   hipGetDevice(&dev);

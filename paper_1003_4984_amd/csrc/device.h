@@ -889,13 +889,13 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
     dr[q] = (ir < nrow) ? rhs[ir * NR + q] : 0.0;
     pr[q] = (prow && ip < nrow) ? rhs[ip * NR + q] : 0.0;
   }
-  double dg = 1.0;
+  double *piv = scr + (T - 1) * TILE_D;   // pivots a_kk of this block column
   double pv = rbcast<0>(d[0]);
   double iv = recip(pv);
   cfor<0, 16>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     ok = ok && (pv > 0.0);
-    const double rs = rsqrt(pv);   // only scales the panel column (off the critical path)
+    piv[k] = pv;                   // same value from every lane
     const double cd = (x > k) ? d[k] * iv : 0.0;
     const double cp = p[k] * iv;
     double pn = 1.0, ivn = 1.0;
@@ -915,8 +915,7 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
       dr[q] = fma(-cd, b, dr[q]);
       if constexpr (J + 1 < T) pr[q] = fma(-cp, b, pr[q]);
     }
-    dg = (x == k) ? pv : dg;
-    p[k] = p[k] * rs;
+    p[k] = cp;                     // the panel keeps c_ik = a_ik / a_kk
     pv = pn;
     iv = ivn;
   });
@@ -930,7 +929,7 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
   }
   // rows of block J are final: y_i = r_i / L_ii (counted once, by row group 0)
   if (rho == 0 && ir < nrow) {
-    const double inv = recip(dg);   // y_i y'_i = r_i r'_i / d_i
+    const double inv = recip(piv[x]);   // y_i y'_i = r_i r'_i / d_i
     const double r0 = dr[0], r1 = dr[1];
     if (SPIN == 0) {
       acc.v0 = fma(r0 * r1, inv, acc.v0);
@@ -948,13 +947,17 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
 #pragma unroll
       for (int q = 0; q < NR; ++q) rhs[ip * NR + q] = pr[q];
     }
-    // panels L_rJ (r > J) to LDS, then into the MFMA operand layout:
-    // fr[r][m] at lane l = L_rJ(l % 16, 4 m + l / 16)
+    // panels C_rJ (c_ik = a_ik / a_kk, r > J) to LDS, then into the MFMA operand
+    // layout: fr[r][m] at lane l = C_rJ(l % 16, 4 m + l / 16).  The trailing
+    // update L_rJ L_sJ^T = sum_k c_ik a_jk takes a_jk = c_jk a_kk as the B operand,
+    // so no square root is needed anywhere in the block column.
     if (prow) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) scr[(rho - 1) * TILE_D + x * TSTR + j] = p[j];
     }
-    double fr[T][4];
+    double fr[T][4], dk[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dk[m] = piv[4 * m + rho];
 #pragma unroll
     for (int r = J + 1; r < T; ++r)
 #pragma unroll
@@ -965,7 +968,7 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
       for (int s = J + 1; s <= r; ++s)
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          S.c[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fr[r][m], fr[s][m], S.c[r][s], 0, 0, 0);
+          S.c[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fr[r][m], fr[s][m] * dk[m], S.c[r][s], 0, 0, 0);
     tile_step<T, SPIN, NR, J + 1>(S, scr, rhs, mat, l, nrow, nug, acc, ok);
   }
 }

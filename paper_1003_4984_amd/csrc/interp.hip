@@ -343,7 +343,7 @@ template <int T, int SPIN, bool FP32>
 static int launch_tile(const Plan *p, const double *map, const double *theta, const double *phi,
                        int64_t n, double *out, double *var, hipStream_t s) {
   constexpr int NR = (SPIN == 0) ? 2 : 3;
-  constexpr int SCR = (T - 1) * TILE_D;   // staged tiles overlay the packed system
+  constexpr int SCR = (T - 1) * TILE_D + 16;   // staged tiles and pivots overlay the packed system
   if (FP32) {
     constexpr int G = 64, PPW = 1;
     const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, PPW, PPW, NR, SCR);
