@@ -118,6 +118,7 @@ __device__ inline T group_bcast(T v, int k, int grp) {
 
 struct RingSpan {
   double z, s, phi0, dphi;
+  double sdiff;   // s_ring - s_target, formed without cancellation
   long long first;
   int n, j0, off, pad;
 };
@@ -226,6 +227,7 @@ __device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st,
       }
       RingSpan S;
       S.z = R.z; S.s = R.s; S.phi0 = R.phi0; S.dphi = R.dphi;
+      S.sdiff = (zt - R.z) * (zt + R.z) / (R.s + st);
       S.first = R.first; S.n = R.n;
       int jm = j0 % R.n;
       if (jm < 0) jm += R.n;
@@ -260,8 +262,7 @@ __device__ int enumerate_disc(const PlanDev &P, double th, double zt, double st,
         const double dphi = S.phi0 + (double)j * S.dphi - phr;
         double sh, ch;
         sincos_bounded(0.5 * dphi, sh, ch);
-        const double sdiff = (zt - S.z) * (zt + S.z) / (S.s + st);   // s_ring - s_target
-        const double dx = sdiff - 2.0 * S.s * sh * sh;
+        const double dx = S.sdiff - 2.0 * S.s * sh * sh;
         const double dy = 2.0 * S.s * sh * ch;
         const double dz = S.z - zt;
         u = 0.5 * (dx * dx + dy * dy + dz * dz);
@@ -859,6 +860,70 @@ struct TileAcc {
   double v0, v1, q0, q1;
 };
 
+// Column updates of one elimination step as v_fmac_f64 with a row_newbcast DPP
+// source: the broadcast value feeds the multiply directly, so no separate move
+// is issued.  For each column j: p_j += ncp * d_j(lane k), then d_j += ncd *
+// d_j(lane k) (lane k's d_j is the pivot row's entry; ncd = 0 on lane k, so the
+// source is unchanged).  Every block starts with s_nop 1, the two wait states a
+// DPP read needs after a VALU write of its source; inside a block no DPP source
+// is written before it is read.
+#define FLINTS_FMAC_DPP(dst, src, c) "v_fmac_f64_dpp " dst ", " src ", " c " row_newbcast:%[k] row_mask:0xf bank_mask:0xf\n\t"
+
+template <int K>
+__device__ __forceinline__ void dpp_pd1(double &p0, double &d0, double ncp, double ncd) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[p0]", "%[d0]", "%[cp]") FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
+                   : [p0] "+v"(p0), [d0] "+v"(d0) : [cp] "v"(ncp), [cd] "v"(ncd), [k] "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void dpp_pd4(double &p0, double &d0, double &p1, double &d1, double &p2, double &d2,
+                                        double &p3, double &d3, double ncp, double ncd) {
+  __asm__ volatile("s_nop 1\n\t"
+                   FLINTS_FMAC_DPP("%[p0]", "%[d0]", "%[cp]") FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[p1]", "%[d1]", "%[cp]") FLINTS_FMAC_DPP("%[d1]", "%[d1]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[p2]", "%[d2]", "%[cp]") FLINTS_FMAC_DPP("%[d2]", "%[d2]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[p3]", "%[d3]", "%[cp]") FLINTS_FMAC_DPP("%[d3]", "%[d3]", "%[cd]")
+                   : [p0] "+v"(p0), [d0] "+v"(d0), [p1] "+v"(p1), [d1] "+v"(d1), [p2] "+v"(p2), [d2] "+v"(d2),
+                     [p3] "+v"(p3), [d3] "+v"(d3)
+                   : [cp] "v"(ncp), [cd] "v"(ncd), [k] "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void dpp_d1(double &d0, double ncd) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
+                   : [d0] "+v"(d0) : [cd] "v"(ncd), [k] "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void dpp_d4(double &d0, double &d1, double &d2, double &d3, double ncd) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]") FLINTS_FMAC_DPP("%[d1]", "%[d1]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[d2]", "%[d2]", "%[cd]") FLINTS_FMAC_DPP("%[d3]", "%[d3]", "%[cd]")
+                   : [d0] "+v"(d0), [d1] "+v"(d1), [d2] "+v"(d2), [d3] "+v"(d3) : [cd] "v"(ncd), [k] "i"(K));
+}
+// Pivot of step K + 1 from lane K + 1, read after the wait states its DPP source
+// needs (it was just updated by the first column block).
+template <int K>
+__device__ __forceinline__ double dpp_pivot(double &dsrc) {
+  double r;
+  __asm__ volatile("s_nop 1\n\tv_mov_b64_dpp %[r], %[s] row_newbcast:%[k] row_mask:0xf bank_mask:0xf"
+                   : [r] "=&v"(r) : [s] "v"(dsrc), [k] "i"(K));
+  return r;
+}
+#undef FLINTS_FMAC_DPP
+
+// Columns J0 .. 15 of step K, in blocks of four.
+template <int K, int J0, bool PANEL>
+__device__ __forceinline__ void dpp_columns(double (&d)[16], double (&p)[16], double ncp, double ncd) {
+  if constexpr (J0 + 4 <= 16) {
+    if constexpr (PANEL)
+      dpp_pd4<K>(p[J0], d[J0], p[J0 + 1], d[J0 + 1], p[J0 + 2], d[J0 + 2], p[J0 + 3], d[J0 + 3], ncp, ncd);
+    else
+      dpp_d4<K>(d[J0], d[J0 + 1], d[J0 + 2], d[J0 + 3], ncd);
+    dpp_columns<K, J0 + 4, PANEL>(d, p, ncp, ncd);
+  } else if constexpr (J0 < 16) {
+    if constexpr (PANEL) dpp_pd1<K>(p[J0], d[J0], ncp, ncd);
+    else dpp_d1<K>(d[J0], ncd);
+    dpp_columns<K, J0 + 1, PANEL>(d, p, ncp, ncd);
+  }
+}
+
 template <int T, int SPIN, int NR, int J>
 __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rhs, const double *mat,
                                           int l, int nrow, double nug, TileAcc &acc, bool &ok) {
@@ -899,16 +964,15 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
     const double cd = (x > k) ? d[k] * iv : 0.0;
     const double cp = p[k] * iv;
     double pn = 1.0, ivn = 1.0;
-    cfor<k + 1, 16>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
-      const double b = rbcast<k>(d[j]);
-      d[j] = fma(-cd, b, d[j]);
-      if constexpr (J + 1 < T) p[j] = fma(-cp, b, p[j]);
-      if constexpr (j == k + 1) {
-        pn = rbcast<j>(d[j]);   // next pivot, final after this update
-        ivn = recip(pn);
-      }
-    });
+    if constexpr (k + 1 < 16) {
+      // column k + 1 first: it holds the next pivot, whose reciprocal then
+      // overlaps the remaining columns
+      if constexpr (J + 1 < T) dpp_pd1<k>(p[k + 1], d[k + 1], -cp, -cd);
+      else dpp_d1<k>(d[k + 1], -cd);
+      pn = dpp_pivot<k + 1>(d[k + 1]);
+      ivn = recip(pn);
+      dpp_columns<k, k + 2, (J + 1 < T)>(d, p, -cp, -cd);
+    }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const double b = rbcast<k>(dr[q]);
