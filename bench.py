@@ -114,13 +114,15 @@ def cpu_baseline(shape, inp, out_t, var_t, out_qu, var_qu, n_sample, seed_cfg):
             return t[idx].cpu().numpy().reshape(np.shape(pix))
         return f
 
-    t0 = time.perf_counter()
-    st = kriging.stencils(nside, th, ph, K)
-    v0, w0, _ = kriging.interpolate(nside, inp["tt"], K, 0, getter(tmap), th, ph, stencil_idx=st)
-    v2, w2, _ = kriging.interpolate(nside, (inp["ee"], inp["bb"]), K, 2,
-                                    (getter(qumap, 0), getter(qumap, npix)), th, ph,
-                                    stencil_idx=st)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):   # the baseline is one host core, BLAS included
+        t0 = time.perf_counter()
+        st = kriging.stencils(nside, th, ph, K)
+        v0, w0, _ = kriging.interpolate(nside, inp["tt"], K, 0, getter(tmap), th, ph, stencil_idx=st)
+        v2, w2, _ = kriging.interpolate(nside, (inp["ee"], inp["bb"]), K, 2,
+                                        (getter(qumap, 0), getter(qumap, npix)), th, ph,
+                                        stencil_idx=st)
+        dt = time.perf_counter() - t0
     sel_t = torch.as_tensor(sel, device=out_t.device)
     g0 = out_t[sel_t].cpu().numpy()
     gv0 = var_t[sel_t].cpu().numpy()
@@ -141,7 +143,7 @@ def cpu_baseline(shape, inp, out_t, var_t, out_qu, var_qu, n_sample, seed_cfg):
     base = {"value": 3.0 * len(sel) / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(sel)} seeded targets of the same N_side {nside} T+Q+U workload "
                       f"(K={K}, exact per-pair correlation sums to lmax {shape['lmax']}), "
-                      f"{dt:.1f} s single-threaded numpy"}
+                      f"{dt:.1f} s of numpy on one host thread (BLAS limited to one)"}
     return base, parity
 
 
@@ -152,7 +154,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="nside4096", choices=sorted(SHAPES))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32ir"])
-    ap.add_argument("--cpu-sample", type=int, default=60)
+    ap.add_argument("--cpu-sample", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy of "
