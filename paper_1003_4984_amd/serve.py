@@ -4,7 +4,7 @@ Requests (a map set -- T, or T with Q/U -- plus displaced target directions)
 arrive over time.  The server keeps plans, and with them the device-resident
 correlation tables, in a cache keyed by (N_side, lmax, K, spin, spectrum); admits
 waiting requests first-come first-served while the HBM they need (outputs,
-variances and any new plan's table) fits a budget and a launch slot is free;
+variances, maps, targets and any new plan's table) fits a budget and a launch slot is free;
 groups the requests admitted at one step into one batched launch
 (flints_batch_*) on the next free stream, so work of different requests
 overlaps on the device; and releases a request's memory when its completion
@@ -53,7 +53,12 @@ class Request:
         return self.n * len(self.fields)
 
     def footprint(self, new_tables=0):
-        return self.samples * BYTES_PER_SAMPLE + new_tables * TABLE_BYTES_BOUND
+        """HBM a request holds while admitted: its maps (f fields of 12 N_side^2
+        doubles), its target directions (16 B each), outputs and variances
+        (16 B per sample) and the tables of plans not yet cached."""
+        f = len(self.fields)
+        return (8 * 12 * self.nside * self.nside * f + 16 * self.n + self.samples * BYTES_PER_SAMPLE
+                + new_tables * TABLE_BYTES_BOUND)
 
 
 class PlanCache:

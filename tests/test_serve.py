@@ -72,7 +72,7 @@ def test_all_served_fifo_and_latency():
 def test_budget_and_slots_respected():
     ns = [5000] * 12
     reqs = _reqs(np.linspace(0, 0.002, 12), ns)
-    budget = 2 * 5000 * BYTES_PER_SAMPLE          # two requests in flight at most
+    budget = 2 * reqs[0].footprint()               # two requests in flight at most
     srv, ex, done, _ = _serve(reqs, budget=budget, slots=3)
     assert len(done) == 12
     assert srv.peak <= budget
@@ -100,7 +100,8 @@ def test_new_plan_tables_count_against_budget():
     r = _reqs([0.0], [100], fields="TQU")[0]
     r.cl_ee, r.cl_bb = np.ones(17), np.zeros(17)
     assert plans.missing(r) == 2
-    assert r.footprint(plans.missing(r)) == 3 * 100 * BYTES_PER_SAMPLE + 2 * TABLE_BYTES_BOUND
+    maps = 8 * 12 * 16 * 16 * 3                      # T, Q, U at N_side 16
+    assert r.footprint(plans.missing(r)) == maps + 16 * 100 + 3 * 100 * BYTES_PER_SAMPLE + 2 * TABLE_BYTES_BOUND
     plans.get(16, 16, 8, 0, r.cl_tt)
     assert plans.missing(r) == 1 and len(plans) == 1
     plans.get(16, 16, 8, 0, r.cl_tt)
