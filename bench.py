@@ -48,14 +48,21 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interp_tile_nside4096_K32
 
 
 def kernel_source_hash():
+    """sha256 of the kernel sources with comments and blank space removed (a
+    change of comments does not change the kernels the counters measured)."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1003_4984_amd", "csrc")
     for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        with open(f) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"\s+", " ", text)
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        h.update(text.encode())
     return h.hexdigest()
 
 
@@ -161,7 +168,7 @@ def main():
                          "known size that calibrates HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

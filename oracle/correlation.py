@@ -11,7 +11,7 @@ Spin 2 (paper Sec. 2.2, Eq. spins_correl, with the Wigner d functions of App. B)
     xi_-(beta) = sum_{l>=2} (2l+1)/(4 pi) (C^EE_l - C^BB_l) d^l_{2,-2}(beta)
 The paper writes only the Hermitian term (xi_+, with d^l_{-s,-s} = d^l_{s,s}); the
 pseudo-covariance xi_- is what an exact Gaussian conditional mean of (Q, U) also
-needs (reading documented in the design doc).
+needs; it is computed here for the full spin-2 mode (the paper mode omits it).
 
 All functions take u = 1 - cos(beta) = |n_a - n_b|^2 / 2 rather than cos(beta):
 near beta = 0 the covariances differ from their zero-lag value by O(l^2 u), and

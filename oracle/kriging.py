@@ -2,7 +2,7 @@
 
 Test infrastructure only (see oracle/__init__.py).  Follows the paper's steps in
 its order (Sec. 2.5, "The interpolation algorithm"), with the stencil rule read as
-"the K nearest pixel centres" (reading in DESIGN.md):
+"the K nearest pixel centres" (chord distance, ties to the smaller RING index):
 
  1. resolution N_side and band limit lmax (given);
  2. the correlation function (oracle.correlation, exact per pair, no table);

@@ -1116,7 +1116,7 @@ __device__ inline void residual64(const double *mat, const double *rhs, int row_
   }
 }
 
-// FP32 + refinement phase B (SURVEY a7/a8): covariance entries stay FP64 in LDS;
+// FP32 + refinement phase B: covariance entries stay FP64 in LDS;
 // S + nI is rounded to FP32 and factorised, w = (S + nI)^-1 b is solved in FP32,
 // one refinement step uses the FP64 residual and an FP32 correction solve, and
 // value / variance use FP64 accumulation with the final FP64 residual r:
