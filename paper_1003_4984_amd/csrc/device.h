@@ -703,6 +703,81 @@ __device__ __forceinline__ void cfor(F &&f) {
   }
 }
 
+// Column updates of one elimination step as v_fmac_f64 with a row_newbcast DPP
+// source: the broadcast value feeds the multiply directly, so no separate move
+// is issued.  For each column j: p_j += ncp * d_j(lane k), then d_j += ncd *
+// d_j(lane k) (lane k's d_j is the pivot row's entry; ncd = 0 on lane k, so the
+// source is unchanged).  Every block starts with s_nop 1, the two wait states a
+// DPP read needs after a VALU write of its source; inside a block no DPP source
+// is written before it is read.
+#define FLINTS_FMAC_DPP(dst, src, c) "v_fmac_f64_dpp " dst ", " src ", " c " row_newbcast:%[k] row_mask:0xf bank_mask:0xf\n\t"
+
+template <int K>
+__device__ __forceinline__ void dpp_pd1(double &p0, double &d0, double ncp, double ncd) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[p0]", "%[d0]", "%[cp]") FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
+                   : [p0] "+v"(p0), [d0] "+v"(d0) : [cp] "v"(ncp), [cd] "v"(ncd), [k] "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void dpp_pd4(double &p0, double &d0, double &p1, double &d1, double &p2, double &d2,
+                                        double &p3, double &d3, double ncp, double ncd) {
+  __asm__ volatile("s_nop 1\n\t"
+                   FLINTS_FMAC_DPP("%[p0]", "%[d0]", "%[cp]") FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[p1]", "%[d1]", "%[cp]") FLINTS_FMAC_DPP("%[d1]", "%[d1]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[p2]", "%[d2]", "%[cp]") FLINTS_FMAC_DPP("%[d2]", "%[d2]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[p3]", "%[d3]", "%[cp]") FLINTS_FMAC_DPP("%[d3]", "%[d3]", "%[cd]")
+                   : [p0] "+v"(p0), [d0] "+v"(d0), [p1] "+v"(p1), [d1] "+v"(d1), [p2] "+v"(p2), [d2] "+v"(d2),
+                     [p3] "+v"(p3), [d3] "+v"(d3)
+                   : [cp] "v"(ncp), [cd] "v"(ncd), [k] "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void dpp_d1(double &d0, double ncd) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
+                   : [d0] "+v"(d0) : [cd] "v"(ncd), [k] "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void dpp_d4(double &d0, double &d1, double &d2, double &d3, double ncd) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]") FLINTS_FMAC_DPP("%[d1]", "%[d1]", "%[cd]")
+                   FLINTS_FMAC_DPP("%[d2]", "%[d2]", "%[cd]") FLINTS_FMAC_DPP("%[d3]", "%[d3]", "%[cd]")
+                   : [d0] "+v"(d0), [d1] "+v"(d1), [d2] "+v"(d2), [d3] "+v"(d3) : [cd] "v"(ncd), [k] "i"(K));
+}
+// Pivot of step K + 1 from lane K + 1, read after the wait states its DPP source
+// needs (it was just updated by the first column block).
+template <int K>
+__device__ __forceinline__ double dpp_pivot(double &dsrc) {
+  double r;
+  __asm__ volatile("s_nop 1\n\tv_mov_b64_dpp %[r], %[s] row_newbcast:%[k] row_mask:0xf bank_mask:0xf"
+                   : [r] "=&v"(r) : [s] "v"(dsrc), [k] "i"(K));
+  return r;
+}
+// dst_t += c_t * src(lane L) for one or two destinations sharing the source.
+template <int L>
+__device__ __forceinline__ void dpp_fma1(double &d0, double src, double c0) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[s]", "%[c0]")
+                   : [d0] "+v"(d0) : [s] "v"(src), [c0] "v"(c0), [k] "i"(L));
+}
+template <int L>
+__device__ __forceinline__ void dpp_fma2(double &d0, double &d1, double src, double c0, double c1) {
+  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[s]", "%[c0]") FLINTS_FMAC_DPP("%[d1]", "%[s]", "%[c1]")
+                   : [d0] "+v"(d0), [d1] "+v"(d1) : [s] "v"(src), [c0] "v"(c0), [c1] "v"(c1), [k] "i"(L));
+}
+#undef FLINTS_FMAC_DPP
+
+// Columns J0 .. 15 of step K, in blocks of four.
+template <int K, int J0, bool PANEL>
+__device__ __forceinline__ void dpp_columns(double (&d)[16], double (&p)[16], double ncp, double ncd) {
+  if constexpr (J0 + 4 <= 16) {
+    if constexpr (PANEL)
+      dpp_pd4<K>(p[J0], d[J0], p[J0 + 1], d[J0 + 1], p[J0 + 2], d[J0 + 2], p[J0 + 3], d[J0 + 3], ncp, ncd);
+    else
+      dpp_d4<K>(d[J0], d[J0 + 1], d[J0 + 2], d[J0 + 3], ncd);
+    dpp_columns<K, J0 + 4, PANEL>(d, p, ncp, ncd);
+  } else if constexpr (J0 < 16) {
+    if constexpr (PANEL) dpp_pd1<K>(p[J0], d[J0], ncp, ncd);
+    else dpp_d1<K>(d[J0], ncd);
+    dpp_columns<K, J0 + 1, PANEL>(d, p, ncp, ncd);
+  }
+}
+
 template <int NT, int NR>
 struct RowSys {
   double a[NT][16 * NT];   // a[t][j] used for j < 16 (t + 1)
@@ -748,6 +823,60 @@ __device__ __forceinline__ void rowsys_load(RowSys<NT, NR> &S, const double *mat
 // step K - 1, which computes them as soon as column K + 1 is final so that the
 // reciprocal overlaps the rest of that step's updates.  dg keeps the pivot of
 // each of the lane's rows: r_i^2 / d_i = y_i^2 needs no square root.
+// Four consecutive columns L0 .. L0 + 3 (one 16-lane block) of a row-group
+// step: dst_t[i] += c_t * src(lane L0 + i), one or two row arrays.
+template <int L0>
+__device__ __forceinline__ void dpp_cols4x1(double &a0, double &a1, double &a2, double &a3, double src, double c0) {
+  __asm__ volatile("s_nop 1\n\t"
+                   "v_fmac_f64_dpp %[a0], %[s], %[c0] row_newbcast:%[l0] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[a1], %[s], %[c0] row_newbcast:%[l1] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[a2], %[s], %[c0] row_newbcast:%[l2] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[a3], %[s], %[c0] row_newbcast:%[l3] row_mask:0xf bank_mask:0xf"
+                   : [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3)
+                   : [s] "v"(src), [c0] "v"(c0), [l0] "i"(L0), [l1] "i"(L0 + 1), [l2] "i"(L0 + 2), [l3] "i"(L0 + 3));
+}
+template <int L0>
+__device__ __forceinline__ void dpp_cols4x2(double &a0, double &a1, double &a2, double &a3, double &b0, double &b1,
+                                            double &b2, double &b3, double src, double c0, double c1) {
+  __asm__ volatile("s_nop 1\n\t"
+                   "v_fmac_f64_dpp %[a0], %[s], %[c0] row_newbcast:%[l0] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[b0], %[s], %[c1] row_newbcast:%[l0] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[a1], %[s], %[c0] row_newbcast:%[l1] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[b1], %[s], %[c1] row_newbcast:%[l1] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[a2], %[s], %[c0] row_newbcast:%[l2] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[b2], %[s], %[c1] row_newbcast:%[l2] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[a3], %[s], %[c0] row_newbcast:%[l3] row_mask:0xf bank_mask:0xf\n\t"
+                   "v_fmac_f64_dpp %[b3], %[s], %[c1] row_newbcast:%[l3] row_mask:0xf bank_mask:0xf"
+                   : [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3), [b0] "+v"(b0), [b1] "+v"(b1),
+                     [b2] "+v"(b2), [b3] "+v"(b3)
+                   : [s] "v"(src), [c0] "v"(c0), [c1] "v"(c1), [l0] "i"(L0), [l1] "i"(L0 + 1), [l2] "i"(L0 + 2),
+                     [l3] "i"(L0 + 3));
+}
+
+// Columns J0 .. N - 1 of row-group step K (after column K + 1, which carries the
+// next pivot): blocks of four within a 16-column block, else one at a time.
+template <int NT, int NR, int K, int J0>
+__device__ __forceinline__ void rowsys_columns(RowSys<NT, NR> &S, const double (&nc)[NT]) {
+  constexpr int N = 16 * NT, TK = K / 16;
+  if constexpr (J0 < N) {
+    constexpr int T0 = (J0 / 16 > TK ? J0 / 16 : TK);
+    if constexpr (J0 % 16 <= 12 && J0 + 4 <= N && (J0 + 3) / 16 == J0 / 16) {
+      if constexpr (T0 + 1 < NT)
+        dpp_cols4x2<J0 % 16>(S.a[T0][J0], S.a[T0][J0 + 1], S.a[T0][J0 + 2], S.a[T0][J0 + 3], S.a[T0 + 1][J0],
+                             S.a[T0 + 1][J0 + 1], S.a[T0 + 1][J0 + 2], S.a[T0 + 1][J0 + 3], S.a[J0 / 16][K],
+                             nc[T0], nc[T0 + 1]);
+      else
+        dpp_cols4x1<J0 % 16>(S.a[T0][J0], S.a[T0][J0 + 1], S.a[T0][J0 + 2], S.a[T0][J0 + 3], S.a[J0 / 16][K],
+                             nc[T0]);
+      rowsys_columns<NT, NR, K, J0 + 4>(S, nc);
+    } else {
+      if constexpr (T0 + 1 < NT) dpp_fma2<J0 % 16>(S.a[T0][J0], S.a[T0 + 1][J0], S.a[J0 / 16][K], nc[T0], nc[T0 + 1]);
+      else dpp_fma1<J0 % 16>(S.a[T0][J0], S.a[J0 / 16][K], nc[T0]);
+      rowsys_columns<NT, NR, K, J0 + 1>(S, nc);
+    }
+  }
+}
+
 template <int NT, int NR, int K>
 __device__ __forceinline__ void rowsys_step(RowSys<NT, NR> &S, double (&dg)[NT], int x, bool &ok,
                                             double d, double inv) {
@@ -757,21 +886,27 @@ __device__ __forceinline__ void rowsys_step(RowSys<NT, NR> &S, double (&dg)[NT],
 #pragma unroll
   for (int t = TK; t < NT; ++t) c[t] = (x + 16 * t > K) ? S.a[t][K] * inv : 0.0;
   double dn = 1.0, invn = 1.0;
-  cfor<K + 1, N>([&](auto jc) {
-    constexpr int j = decltype(jc)::value;
-    const double b = rbcast<j % 16>(S.a[j / 16][K]);
+  double nc[NT];
 #pragma unroll
-    for (int t = (j / 16 > TK ? j / 16 : TK); t < NT; ++t) S.a[t][j] = fma(-c[t], b, S.a[t][j]);
-    if constexpr (j == K + 1) {
-      dn = rbcast<j % 16>(S.a[j / 16][j]);   // next pivot, final after this update
-      invn = recip(dn);
-    }
-  });
+  for (int t = TK; t < NT; ++t) nc[t] = -c[t];
+  // column j takes a_ij -= c_i a_jK for the lane's rows i = x + 16 t >= j; the
+  // source a_jK is lane j % 16's register a[j / 16][K], fed to the FMAs by DPP
+  static_assert(NT <= 2, "row-group engine holds at most two row arrays");
+  if constexpr (K + 1 < N) {
+    constexpr int j = K + 1, T0 = (j / 16 > TK ? j / 16 : TK);
+    if constexpr (T0 + 1 < NT) dpp_fma2<j % 16>(S.a[T0][j], S.a[T0 + 1][j], S.a[j / 16][K], nc[T0], nc[T0 + 1]);
+    else dpp_fma1<j % 16>(S.a[T0][j], S.a[j / 16][K], nc[T0]);
+    dn = dpp_pivot<j % 16>(S.a[j / 16][j]);   // next pivot, final after this update
+    invn = recip(dn);
+    rowsys_columns<NT, NR, K, K + 2>(S, nc);
+  }
+  // right-hand sides: the source r[TK][q] of lane XK is also a destination, so
+  // the other array is updated first (no DPP read after a write of its source;
+  // lane XK's own r[TK][q] is unchanged since its coefficient is zero)
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
-    const double b = rbcast<XK>(S.r[TK][q]);
-#pragma unroll
-    for (int t = TK; t < NT; ++t) S.r[t][q] = fma(-c[t], b, S.r[t][q]);
+    if constexpr (TK + 1 < NT) dpp_fma2<XK>(S.r[TK + 1][q], S.r[TK][q], S.r[TK][q], nc[TK + 1], nc[TK]);
+    else dpp_fma1<XK>(S.r[TK][q], S.r[TK][q], nc[TK]);
   }
   dg[TK] = (x == XK) ? d : dg[TK];
   if constexpr (K + 1 < N) rowsys_step<NT, NR, K + 1>(S, dg, x, ok, dn, invn);
@@ -860,70 +995,6 @@ struct TileAcc {
   double v0, v1, q0, q1;
 };
 
-// Column updates of one elimination step as v_fmac_f64 with a row_newbcast DPP
-// source: the broadcast value feeds the multiply directly, so no separate move
-// is issued.  For each column j: p_j += ncp * d_j(lane k), then d_j += ncd *
-// d_j(lane k) (lane k's d_j is the pivot row's entry; ncd = 0 on lane k, so the
-// source is unchanged).  Every block starts with s_nop 1, the two wait states a
-// DPP read needs after a VALU write of its source; inside a block no DPP source
-// is written before it is read.
-#define FLINTS_FMAC_DPP(dst, src, c) "v_fmac_f64_dpp " dst ", " src ", " c " row_newbcast:%[k] row_mask:0xf bank_mask:0xf\n\t"
-
-template <int K>
-__device__ __forceinline__ void dpp_pd1(double &p0, double &d0, double ncp, double ncd) {
-  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[p0]", "%[d0]", "%[cp]") FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
-                   : [p0] "+v"(p0), [d0] "+v"(d0) : [cp] "v"(ncp), [cd] "v"(ncd), [k] "i"(K));
-}
-template <int K>
-__device__ __forceinline__ void dpp_pd4(double &p0, double &d0, double &p1, double &d1, double &p2, double &d2,
-                                        double &p3, double &d3, double ncp, double ncd) {
-  __asm__ volatile("s_nop 1\n\t"
-                   FLINTS_FMAC_DPP("%[p0]", "%[d0]", "%[cp]") FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
-                   FLINTS_FMAC_DPP("%[p1]", "%[d1]", "%[cp]") FLINTS_FMAC_DPP("%[d1]", "%[d1]", "%[cd]")
-                   FLINTS_FMAC_DPP("%[p2]", "%[d2]", "%[cp]") FLINTS_FMAC_DPP("%[d2]", "%[d2]", "%[cd]")
-                   FLINTS_FMAC_DPP("%[p3]", "%[d3]", "%[cp]") FLINTS_FMAC_DPP("%[d3]", "%[d3]", "%[cd]")
-                   : [p0] "+v"(p0), [d0] "+v"(d0), [p1] "+v"(p1), [d1] "+v"(d1), [p2] "+v"(p2), [d2] "+v"(d2),
-                     [p3] "+v"(p3), [d3] "+v"(d3)
-                   : [cp] "v"(ncp), [cd] "v"(ncd), [k] "i"(K));
-}
-template <int K>
-__device__ __forceinline__ void dpp_d1(double &d0, double ncd) {
-  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]")
-                   : [d0] "+v"(d0) : [cd] "v"(ncd), [k] "i"(K));
-}
-template <int K>
-__device__ __forceinline__ void dpp_d4(double &d0, double &d1, double &d2, double &d3, double ncd) {
-  __asm__ volatile("s_nop 1\n\t" FLINTS_FMAC_DPP("%[d0]", "%[d0]", "%[cd]") FLINTS_FMAC_DPP("%[d1]", "%[d1]", "%[cd]")
-                   FLINTS_FMAC_DPP("%[d2]", "%[d2]", "%[cd]") FLINTS_FMAC_DPP("%[d3]", "%[d3]", "%[cd]")
-                   : [d0] "+v"(d0), [d1] "+v"(d1), [d2] "+v"(d2), [d3] "+v"(d3) : [cd] "v"(ncd), [k] "i"(K));
-}
-// Pivot of step K + 1 from lane K + 1, read after the wait states its DPP source
-// needs (it was just updated by the first column block).
-template <int K>
-__device__ __forceinline__ double dpp_pivot(double &dsrc) {
-  double r;
-  __asm__ volatile("s_nop 1\n\tv_mov_b64_dpp %[r], %[s] row_newbcast:%[k] row_mask:0xf bank_mask:0xf"
-                   : [r] "=&v"(r) : [s] "v"(dsrc), [k] "i"(K));
-  return r;
-}
-#undef FLINTS_FMAC_DPP
-
-// Columns J0 .. 15 of step K, in blocks of four.
-template <int K, int J0, bool PANEL>
-__device__ __forceinline__ void dpp_columns(double (&d)[16], double (&p)[16], double ncp, double ncd) {
-  if constexpr (J0 + 4 <= 16) {
-    if constexpr (PANEL)
-      dpp_pd4<K>(p[J0], d[J0], p[J0 + 1], d[J0 + 1], p[J0 + 2], d[J0 + 2], p[J0 + 3], d[J0 + 3], ncp, ncd);
-    else
-      dpp_d4<K>(d[J0], d[J0 + 1], d[J0 + 2], d[J0 + 3], ncd);
-    dpp_columns<K, J0 + 4, PANEL>(d, p, ncp, ncd);
-  } else if constexpr (J0 < 16) {
-    if constexpr (PANEL) dpp_pd1<K>(p[J0], d[J0], ncp, ncd);
-    else dpp_d1<K>(d[J0], ncd);
-    dpp_columns<K, J0 + 1, PANEL>(d, p, ncp, ncd);
-  }
-}
-
 template <int T, int SPIN, int NR, int J>
 __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rhs, const double *mat,
                                           int l, int nrow, double nug, TileAcc &acc, bool &ok) {
@@ -975,9 +1046,8 @@ __device__ __forceinline__ void tile_step(TileSys<T> &S, double *scr, double *rh
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const double b = rbcast<k>(dr[q]);
-      dr[q] = fma(-cd, b, dr[q]);
-      if constexpr (J + 1 < T) pr[q] = fma(-cp, b, pr[q]);
+      if constexpr (J + 1 < T) dpp_pd1<k>(pr[q], dr[q], -cp, -cd);
+      else dpp_d1<k>(dr[q], -cd);
     }
     p[k] = cp;                     // the panel keeps c_ik = a_ik / a_kk
     pv = pn;
