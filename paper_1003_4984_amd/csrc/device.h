@@ -457,11 +457,16 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
       rhs[(ra + 1) * NR + 2] = nb[9 * ns + a];
     }
   }
-  // off-diagonal pair q = (a - 1)(a - 2) / 2 + (b - 1); lanes stride by WAVE
+  // off-diagonal pair q = (a - 1)(a - 2) / 2 + (b - 1), 0 <= q < K (K - 1) / 2,
+  // lanes stride by WAVE; (a, b) comes from q in closed form, so the loop has a
+  // fixed trip count
   const int npairs = K * (K - 1) / 2;
-  int a = 2, b = 1 + lane;
-  while (b >= a) { b -= a - 1; ++a; }
+#pragma unroll 1
   for (int q = lane; q < npairs; q += WAVE) {
+    int m = (int)(0.5f * (1.0f + sqrtf(1.0f + 8.0f * (float)q)));   // m = a - 1
+    m -= (m * (m - 1) / 2 > q);
+    m += ((m + 1) * m / 2 <= q);
+    const int a = m + 1, b = q - m * (m - 1) / 2 + 1;
     double c[4];
     range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, b, paper, c);
     if (SPIN == 0) {
@@ -473,8 +478,6 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
       mat[tri(ra + 1) + rb] = c[2];
       mat[tri(ra + 1) + rb + 1] = c[3];
     }
-    b += WAVE;
-    while (b >= a) { b -= a - 1; ++a; }
   }
   count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
 }
