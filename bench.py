@@ -8,9 +8,10 @@ damped acoustic spectra, 2.5' rms lensing deflection) are generated on the GPU
 before timing and stay resident in HBM.
 
 Prints ONE JSON line.  `value` counts interpolated field samples (T, Q and U
-separately) per second.  `roofline` is the dominant kernel's (the spin-2
-interpolation) algorithmic FP64 flop rate, timed with HIP events on the launch
-stream, against the MI355X FP64 vector peak.  `cpu_baseline` is the FP64 CPU
+separately) per second.  `roofline` is the dominant kernel's algorithmic FP64
+flop rate (the fused T+Q/U launch, or with --tqu separate the spin-2 launch),
+timed with HIP events on the launch stream, against the MI355X FP64 vector
+peak.  `cpu_baseline` is the FP64 CPU
 oracle on a bounded sample of the same workload, which also serves as a
 sampled parity check of this very run.
 """
@@ -44,7 +45,12 @@ def flops_spin2(K):
     return 16.0 / 3.0 * K ** 3 + 16 * K ** 2 + 60 * (K * (K + 1) / 2 + K)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interp_tile_nside4096_K32.md")
+# Counter summaries of the dominant launch per T+Q+U mode (fused: one launch
+# for all three fields; separate: the spin-2 launch).
+TRAFFIC_FILES = {
+    "fused": os.path.join(ROOT, "profiles", "traffic_interp_tqu_nside4096_K32.md"),
+    "separate": os.path.join(ROOT, "profiles", "traffic_interp_tile_nside4096_K32.md"),
+}
 
 
 def kernel_source_hash():
@@ -66,14 +72,15 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the spin-2 kernel from the committed counter
+def measured_traffic(workload, mode="fused"):
+    """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if that summary
     is for other kernel sources or another workload."""
-    if workload != "nside4096" or not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES[mode]
+    if workload != "nside4096" or not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
                 k, v = line.split(":", 1)
@@ -163,6 +170,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32ir"])
     ap.add_argument("--cpu-sample", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tqu", default="fused", choices=["fused", "separate"],
+                    help="T and Q/U in one launch sharing the stencil search (fused), or one "
+                         "launch per plan (separate)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy of "
                          "known size that calibrates HBM traffic counters)")
@@ -197,9 +207,18 @@ def main():
     var_qu = torch.empty(2 * n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
+    fused = args.tqu == "fused"
+
     def step(ev=None):
         if ev:
             ev[0].record(stream)
+        if fused:
+            fl.interpolate_tqu(p0, p2, inp["T"], inp["QU"], inp["theta"], inp["phi"], out_t=out_t,
+                               var_t=var_t, out_qu=out_qu, var_qu=var_qu, stream=stream)
+            if ev:
+                ev[1].record(stream)
+                ev[2].record(stream)
+            return
         fl.interpolate(p0, inp["T"], inp["theta"], inp["phi"], out=out_t, var=var_t, stream=stream)
         if ev:
             ev[1].record(stream)
@@ -227,8 +246,18 @@ def main():
     st0, st2 = p0.stats(), p2.stats()
 
     K = shape["K"]
-    f2 = flops_spin2(K) * n
-    achieved = f2 / t_spin2.mean() / 1e12
+    if fused:
+        fpp = flops_spin0(K) + flops_spin2(K)
+        achieved = fpp * n / t_spin0.mean() / 1e12
+        kname = "fused T+Q/U launch (k_interp_tqu<2,0,4> + two fix-up scans)"
+        kernel_s = {"tqu": float(t_spin0.mean())}
+        tunit = "HBM bytes per fused T+Q/U launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)"
+    else:
+        fpp = flops_spin2(K)
+        achieved = fpp * n / t_spin2.mean() / 1e12
+        kname = "spin-2 interpolation launch (k_interp_tile<4,2> + fix-up scan)"
+        kernel_s = {"spin0": float(t_spin0.mean()), "spin2": float(t_spin2.mean())}
+        tunit = "HBM bytes per spin-2 launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)"
     result = {
         "metric": "interpolated T/Q/U samples/sec at Nside=4096 within 2e-4 rel err; p50/p99 latency",
         "value": 3.0 * n * args.steps / wall,
@@ -244,18 +273,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"lensing remap N_side {shape['nside']} lmax {shape['lmax']} "
                                f"K {K} T+Q+U, one displaced target per pixel",
-                   "points": n, "precision": args.precision, "spin2_mode": "full",
+                   "points": n, "precision": args.precision, "spin2_mode": "full", "tqu": args.tqu,
                    "nugget": "always (eps = 2^-26)"},
         "points_per_s": n * args.steps / wall,
         "latency_s": {"p50": float(np.percentile(step_t, 50)), "p99": float(np.percentile(step_t, 99)),
-                      "note": "per full-sky request (T then Q/U launch), HIP events"},
-        "kernel_s": {"spin0": float(t_spin0.mean()), "spin2": float(t_spin2.mean())},
+                      "note": "per full-sky request (T, Q and U), HIP events"},
+        "kernel_s": kernel_s,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(args.workload),
-                     "traffic_unit": "HBM bytes per spin-2 launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                     "kernel": "spin-2 interpolation launch (k_interp_tile<4,2> + fix-up scan)",
-                     "flops_per_point": flops_spin2(K)},
+                     "traffic": measured_traffic(args.workload, args.tqu),
+                     "traffic_unit": tunit, "kernel": kname, "flops_per_point": fpp},
         "stats": {"spin0": st0, "spin2": st2},
     }
     if not args.no_cpu and args.cpu_sample > 0:

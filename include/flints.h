@@ -125,6 +125,40 @@ int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
                        const double *phi, int64_t n, void *out, void *var, void *stream);
 
 /*
+ * Temperature and polarisation at the same targets (T + Q + U) with one
+ * stencil search per target.  The stencil of a target (its K nearest pixel
+ * centres, paper Sec. 2.5, step 4) depends only on the target, N_side and K,
+ * so for a spin-0 plan and a spin-2 plan of equal N_side and K the spin-2 pass
+ * writes each target's stencil to device memory and the spin-0 pass reads it
+ * instead of searching again.  Everything after the search is the per-plan
+ * arithmetic of flints_interpolate, and the outputs equal
+ * flints_interpolate(plan_t, map_t, ...) followed by
+ * flints_interpolate(plan_qu, map_qu, ...) bit for bit.
+ *   plan_t   spin-0 plan; plan_qu spin-2 plan with the same nside and K.
+ *   map_t    device double[npix]; map_qu device double[2*npix] (Q then U).
+ *   theta, phi  device double[n], shared by both fields.
+ *   out_t    device double[n]; out_qu device double[2*n] = (Q[n], U[n]).
+ *   var_t, var_qu  device, nullable, same layouts as the outputs.
+ * The search is shared when both plans are FLINTS_FP64 with paper variance
+ * (or their variance is not requested) and their search radii agree (see
+ * flints_tqu_fused); other plan pairs, or a failed allocation of the stencil
+ * buffer, run as the two separate calls on the same stream.  The buffer holds
+ * K ints per target for chunks of up to 2^24 targets (2 GiB at K = 32) and is
+ * allocated and freed on the stream (hipMallocAsync / hipFreeAsync).  Invalid
+ * targets and failed searches are counted in both plans.  Returns
+ * FLINTS_EINVAL for NULL plans or pointers, spins other than (0, 2), or
+ * differing nside or K; n = 0 is a no-op.
+ */
+int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
+                           const void *map_qu, const double *theta, const double *phi, int64_t n,
+                           void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream);
+
+/* 1 if flints_interpolate_tqu shares the stencil search between these plans
+ * (with_var_*: whether variances will be requested), 0 if it runs two
+ * separate calls, < 0 on error.  Host-only; launches nothing. */
+int flints_tqu_fused(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu);
+
+/*
  * Stencil of each target: the K nearest RING pixels, ascending distance, ties to
  * the smaller index (paper Sec. 2.3 step, read as K nearest).
  *   idx    device int64[n*K], row-major; rows of invalid targets are -1.

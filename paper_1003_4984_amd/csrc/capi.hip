@@ -157,6 +157,39 @@ int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
                             (hipStream_t)stream);
 }
 
+int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
+                           const void *map_qu, const double *theta, const double *phi, int64_t n,
+                           void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream) {
+  g_last_error.clear();
+  if (!plan_t || !plan_qu) { set_error("plans must be non-NULL"); return FLINTS_EINVAL; }
+  const Plan *p0 = as_plan(plan_t), *p2 = as_plan(plan_qu);
+  if (p0->d.spin != 0 || p2->d.spin != 2) {
+    set_error("plan_t must be a spin-0 plan and plan_qu a spin-2 plan");
+    return FLINTS_EINVAL;
+  }
+  if (p0->d.nside != p2->d.nside || p0->d.K != p2->d.K) {
+    set_error("plan_t and plan_qu must have the same nside and K");
+    return FLINTS_EINVAL;
+  }
+  if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
+  if (n == 0) return FLINTS_OK;
+  if (!map_t || !map_qu || !theta || !phi || !out_t || !out_qu) {
+    set_error("maps, theta, phi and outputs must be non-NULL");
+    return FLINTS_EINVAL;
+  }
+  return launch_interpolate_tqu(p0, p2, (const double *)map_t, (const double *)map_qu, theta, phi, n,
+                                (double *)out_t, (double *)var_t, (double *)out_qu, (double *)var_qu,
+                                (hipStream_t)stream);
+}
+
+int flints_tqu_fused(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu) {
+  g_last_error.clear();
+  if (!plan_t || !plan_qu) { set_error("plans must be non-NULL"); return FLINTS_EINVAL; }
+  const double some = 0.0;   // stands for a variance array; only its presence matters
+  return tqu_fusable(as_plan(plan_t), as_plan(plan_qu), with_var_t ? &some : nullptr,
+                     with_var_qu ? &some : nullptr) ? 1 : 0;
+}
+
 int flints_stencil(flints_plan_t plan, const double *theta, const double *phi, int64_t n,
                    int64_t *idx, void *stream) {
   g_last_error.clear();

@@ -1318,35 +1318,30 @@ struct TileEngine {
 
 
 // ---------------------------------------------------------------- shared bodies
-// Four points (first at p0) on the wave's row groups: search all, then assemble
-// each into the wave's system buffer and load it into its row group, then
-// phase B for all four at once.
+// Phase A (assembly) and phase B of the four points starting at p0 on the
+// wave's row groups, their stencils already in sel[q K] (bit q of act_mask set
+// where the search succeeded): each is assembled in the wave's single system
+// buffer and loaded into its row group before the next point reuses the buffer,
+// then phase B runs for all four at once.
 template <int NT, int SPIN>
-__device__ inline void group_rs(const PlanDev &P, const double *tab, const double *__restrict__ map,
-                                const double *__restrict__ theta, const double *__restrict__ phi,
-                                int64_t n, double *__restrict__ out, double *__restrict__ var,
-                                const WaveBufs &B, int64_t p0, int lane) {
+__device__ inline void group_rs_solve(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                                      const double *__restrict__ theta, const double *__restrict__ phi,
+                                      int64_t n, double *__restrict__ out, double *__restrict__ var,
+                                      const WaveBufs &B, const int *sel, int64_t p0, int lane,
+                                      unsigned act_mask) {
   constexpr int PPW = 4;
   constexpr int NR = (SPIN == 0) ? 2 : 3;
   const int grp = lane >> 4;
   const int x = lane & 15;
   const int nrow = P.n, K = P.K;
   const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
-  unsigned act_mask = 0;
-#pragma unroll 1
-  for (int q = 0; q < PPW; ++q) {
-    const int64_t pt = p0 + q;
-    if (pt >= n) break;
-    if (phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K))
-      act_mask |= 1u << q;
-  }
   RowSys<NT, NR> S;
   rowsys_identity(S, x);
 #pragma unroll 1
   for (int q = 0; q < PPW; ++q) {
     if (!((act_mask >> q) & 1u)) continue;
     const int64_t pt = p0 + q;
-    phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, B.sel + q * K, B.nb, B.mat, B.rhs);
+    phase_a_build<SPIN, NR>(P, tab, map, theta[pt], phi[pt], lane, sel + q * K, B.nb, B.mat, B.rhs);
     if (grp == q) rowsys_load(S, B.mat, B.rhs, x, nrow, nug);
   }
   GroupOut o;
@@ -1358,23 +1353,133 @@ __device__ inline void group_rs(const PlanDev &P, const double *tab, const doubl
   }
 }
 
+// Four points (first at p0) on the wave's row groups: search all, then
+// assemble and solve them together.
+template <int NT, int SPIN>
+__device__ inline void group_rs(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                                const double *__restrict__ theta, const double *__restrict__ phi,
+                                int64_t n, double *__restrict__ out, double *__restrict__ var,
+                                const WaveBufs &B, int64_t p0, int lane) {
+  constexpr int PPW = 4;
+  const int K = P.K;
+  unsigned act_mask = 0;
+#pragma unroll 1
+  for (int q = 0; q < PPW; ++q) {
+    const int64_t pt = p0 + q;
+    if (pt >= n) break;
+    if (phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K))
+      act_mask |= 1u << q;
+  }
+  group_rs_solve<NT, SPIN>(P, tab, map, theta, phi, n, out, var, B, B.sel, p0, lane, act_mask);
+}
+
+// Assembly, blocked tile Cholesky and output of one point on the whole wave,
+// its stencil already in sel (found is false if the search failed).
+template <int T, int SPIN>
+__device__ inline void tile_solve(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                                  double th, double ph, int64_t n, double *__restrict__ out,
+                                  double *__restrict__ var, const WaveBufs &B, const int *sel,
+                                  int64_t pt, bool found, int lane) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+  GroupOut o;
+  bool ok = true;
+  if (found) {
+    phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, sel, B.nb, B.mat, B.rhs);
+    ok = tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o);
+  }
+  if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
+}
+
 // One point on the whole wave with the blocked tile Cholesky.
 template <int T, int SPIN>
 __device__ inline void point_tile(const PlanDev &P, const double *tab, const double *__restrict__ map,
                                   const double *__restrict__ theta, const double *__restrict__ phi,
                                   int64_t n, double *__restrict__ out, double *__restrict__ var,
                                   const WaveBufs &B, int64_t pt, int lane) {
-  constexpr int NR = (SPIN == 0) ? 2 : 3;
-  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
   const double th = theta[pt], ph = phi[pt];
   const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
-  GroupOut o;
-  bool ok = true;
-  if (found) {
-    phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
-    ok = tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o);
+  tile_solve<T, SPIN>(P, tab, map, th, ph, n, out, var, B, B.sel, pt, found, lane);
+}
+
+// ---------------------------------------------------------------- shared stencils (T + Q/U)
+// The K-nearest stencil of a target depends only on the target, N_side and K
+// (paper Sec. 2.5 picks the neighbours before any covariance is formed).  For
+// temperature and polarisation at the same targets, the spin-2 pass writes each
+// target's stencil to device memory and the spin-0 pass reads it instead of
+// searching again.  stn holds K pixel indices per target of the chunk that
+// starts at target s0; all K entries are -1 where the search failed or the
+// target is invalid.
+__device__ inline void store_stencil(int *__restrict__ stn, int64_t i, int K, const int *sel, bool found,
+                                     int lane) {
+  for (int k = lane; k < K; k += WAVE) stn[i * K + k] = found ? sel[k] : -1;
+}
+
+// point_tile that also writes the stencil.
+template <int T, int SPIN>
+__device__ inline void point_tile_st(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                                     const double *__restrict__ theta, const double *__restrict__ phi,
+                                     int64_t n, double *__restrict__ out, double *__restrict__ var,
+                                     const WaveBufs &B, int64_t pt, int lane, int *__restrict__ stn,
+                                     int64_t s0) {
+  const double th = theta[pt], ph = phi[pt];
+  const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
+  store_stencil(stn, pt - s0, P.K, B.sel, found, lane);
+  tile_solve<T, SPIN>(P, tab, map, th, ph, n, out, var, B, B.sel, pt, found, lane);
+}
+
+// group_rs that also writes the stencils.
+template <int NT, int SPIN>
+__device__ inline void group_rs_st(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                                   const double *__restrict__ theta, const double *__restrict__ phi,
+                                   int64_t n, double *__restrict__ out, double *__restrict__ var,
+                                   const WaveBufs &B, int64_t p0, int lane, int *__restrict__ stn,
+                                   int64_t s0) {
+  constexpr int PPW = 4;
+  const int K = P.K;
+  unsigned act_mask = 0;
+#pragma unroll 1
+  for (int q = 0; q < PPW; ++q) {
+    const int64_t pt = p0 + q;
+    if (pt >= n) break;
+    const bool found = phase_a_search(P, theta[pt], phi[pt], lane, B.cu, B.ci, B.rs, B.sel + q * K);
+    store_stencil(stn, pt - s0, K, B.sel + q * K, found, lane);
+    if (found) act_mask |= 1u << q;
   }
-  if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
+  group_rs_solve<NT, SPIN>(P, tab, map, theta, phi, n, out, var, B, B.sel, p0, lane, act_mask);
+}
+
+// group_rs with the stencils read from stn instead of searched.  Validity is
+// checked and counted as in the search, so the plan's counters are those of a
+// searching pass.
+template <int NT, int SPIN>
+__device__ inline void group_rs_ld(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                                   const double *__restrict__ theta, const double *__restrict__ phi,
+                                   int64_t n, double *__restrict__ out, double *__restrict__ var,
+                                   const WaveBufs &B, int64_t p0, int lane, const int *__restrict__ stn,
+                                   int64_t s0) {
+  constexpr int PPW = 4;
+  const int K = P.K;
+  unsigned act_mask = 0;
+#pragma unroll 1
+  for (int q = 0; q < PPW; ++q) {
+    const int64_t pt = p0 + q;
+    if (pt >= n) break;
+    const double th = theta[pt], ph = phi[pt];
+    const bool good = (th >= 0.0) && (th <= kconst(PI_D)) && isfinite(ph);
+    if (!good) {
+      if (lane == 0) atomicAdd(P.counters + CNT_BAD_INPUT, 1ull);
+      continue;
+    }
+    const int *src = stn + (pt - s0) * K;
+    if (src[0] < 0) {
+      if (lane == 0) atomicAdd(P.counters + CNT_SEARCH_FAIL, 1ull);
+      continue;
+    }
+    for (int k = lane; k < K; k += WAVE) B.sel[q * K + k] = src[k];
+    act_mask |= 1u << q;
+  }
+  group_rs_solve<NT, SPIN>(P, tab, map, theta, phi, n, out, var, B, B.sel, p0, lane, act_mask);
 }
 
 // Fix-up of the 64 outputs starting at p0 (row-group and tile paths): each

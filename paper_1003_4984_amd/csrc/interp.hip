@@ -206,6 +206,60 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
     point_tile<T, SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
 }
 
+// Main passes of T + Q/U over targets [s0, s1) with shared stencils: the
+// spin-2 pass (tiles, or row groups for 2K <= 32 rows) writes each target's
+// stencil to stn, the spin-0 pass (row groups) reads it.  s0 is a multiple of
+// 4 and s1 is a multiple of 4 or n, so no group of four crosses a chunk.
+template <int T>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile_st(
+    PlanDev P, const double *__restrict__ map, const double *__restrict__ theta,
+    const double *__restrict__ phi, int64_t n, double *__restrict__ out, double *__restrict__ var,
+    Layout L, int *__restrict__ stn, int64_t s0, int64_t s1) {
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  for (int64_t pt = s0 + xcd_block() * wpb + wave; pt < s1; pt += (int64_t)gridDim.x * wpb)
+    point_tile_st<T, 2>(P, tab, map, theta, phi, n, out, var, B, pt, lane, stn, s0);
+}
+
+template <int NT>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs_st(
+    PlanDev P, const double *__restrict__ map, const double *__restrict__ theta,
+    const double *__restrict__ phi, int64_t n, double *__restrict__ out, double *__restrict__ var,
+    Layout L, int *__restrict__ stn, int64_t s0, int64_t s1) {
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  const int64_t ngroups = (s1 - s0 + 3) / 4;
+  for (int64_t g = xcd_block() * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb)
+    group_rs_st<NT, 2>(P, tab, map, theta, phi, n, out, var, B, s0 + g * 4, lane, stn, s0);
+}
+
+template <int NT>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs_ld(
+    PlanDev P, const double *__restrict__ map, const double *__restrict__ theta,
+    const double *__restrict__ phi, int64_t n, double *__restrict__ out, double *__restrict__ var,
+    Layout L, const int *__restrict__ stn, int64_t s0, int64_t s1) {
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = load_table(lds, P);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  const int64_t ngroups = (s1 - s0 + 3) / 4;
+  for (int64_t g = xcd_block() * wpb + wave; g < ngroups; g += (int64_t)gridDim.x * wpb)
+    group_rs_ld<NT, 0>(P, tab, map, theta, phi, n, out, var, B, s0 + g * 4, lane, stn, s0);
+}
+
 // Stencil only (a2/a3): K nearest pixel indices per target.
 __global__ __launch_bounds__(STENCIL_WPB * WAVE) void k_stencil(PlanDev P, const double *__restrict__ theta,
                                                  const double *__restrict__ phi, int64_t n,
@@ -255,14 +309,16 @@ static DevLimits device_limits() {
 // Launches the main pass and the fix-up pass over the same LDS layout.  Waves
 // per block: the count that puts the most waves on a CU given the LDS (table
 // shared per block) and the kernel's register use; cached per kernel and layout.
-template <typename KM, typename KE>
-static int launch_pair(KM kern, KE esc, const Plan *p, const Layout &L, int ppw, const double *map,
-                       const double *theta, const double *phi, int64_t n, double *out, double *var,
-                       hipStream_t s) {
-  const DevLimits lim = device_limits();
+// Waves per block for kernel kern over layout L: the count that puts the most
+// waves on a CU given the LDS (tables shared per block) and the kernel's
+// register use; cached per kernel and layout.  Returns false (error set) if
+// not even one wave fits.
+template <typename KM>
+static bool pick_wpb(KM kern, const Layout &L, const DevLimits &lim, int &wpb, int &occ) {
   static std::mutex mu;
   static std::map<std::tuple<int, const void *, int, int>, std::pair<int, int>> cache;
-  int wpb = 0, occ = 0;
+  wpb = 0;
+  occ = 0;
   {
     std::lock_guard<std::mutex> g(mu);
     int dev = 0;
@@ -287,11 +343,22 @@ static int launch_pair(KM kern, KE esc, const Plan *p, const Layout &L, int ppw,
   }
   if (wpb == 0) {
     set_error("plan needs more LDS than the device offers (reduce K or the table size)");
-    return FLINTS_ELIMIT;
+    return false;
   }
+  if (occ < 1) occ = 1;
+  return true;
+}
+
+// Launches the main pass and the fix-up pass over the same LDS layout.
+template <typename KM, typename KE>
+static int launch_pair(KM kern, KE esc, const Plan *p, const Layout &L, int ppw, const double *map,
+                       const double *theta, const double *phi, int64_t n, double *out, double *var,
+                       hipStream_t s) {
+  const DevLimits lim = device_limits();
+  int wpb = 0, occ = 0;
+  if (!pick_wpb(kern, L, lim, wpb, occ)) return FLINTS_ELIMIT;
   const int lds = L.tab_bytes + wpb * L.wave_bytes;
   hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (occ < 1) occ = 1;
   const int64_t ngroups = (n + ppw - 1) / ppw;
   int64_t blocks = std::min<int64_t>((ngroups + wpb - 1) / wpb, (int64_t)lim.ncu * occ);
   if (blocks < 1) blocks = 1;
@@ -386,6 +453,106 @@ int launch_interpolate(const Plan *p, const double *map, const double *theta, co
   if (n == 0) return FLINTS_OK;
   if (p->d.spin == 0) return launch_prec<0>(p, map, theta, phi, n, out, var, s);
   return launch_prec<2>(p, map, theta, phi, n, out, var, s);
+}
+
+// Targets per chunk of the shared-stencil T + Q/U path (a multiple of 4; the
+// stencil buffer holds K ints per target of one chunk: 2 GiB at K = 32).
+constexpr int64_t TQU_CHUNK = int64_t(1) << 24;
+
+// Shared-stencil T + Q/U: per chunk the spin-2 main pass (which writes the
+// stencils) and then the spin-0 main pass (which reads them), each with the
+// layout and block size of its single-plan path; then both fix-up passes.
+// The stencil buffer is stream-ordered (allocated and freed on s); if it
+// cannot be allocated, each plan runs its own searching pass.
+template <int NT0, int NT2, int T2>
+static int launch_tqu_t(const Plan *p0, const Plan *p2, const double *map0, const double *map2,
+                        const double *theta, const double *phi, int64_t n, double *out0, double *var0,
+                        double *out2, double *var2, hipStream_t s) {
+  constexpr int SCR = T2 ? (T2 - 1) * TILE_D + 16 : 0;
+  constexpr int PPW2 = T2 ? 1 : 4;
+  const DevLimits lim = device_limits();
+  const int K = p0->d.K;
+  const Layout L2 = make_layout(p2->d.ntab, p2->d.nfun, K, p2->d.n, PPW2, 1, 3, SCR);
+  const Layout L0 = make_layout(p0->d.ntab, p0->d.nfun, K, p0->d.n, 4, 1, 2);
+  auto k2 = [] {
+    if constexpr (T2 != 0) return k_interp_tile_st<T2>;
+    else return k_interp_rs_st<NT2>;
+  }();
+  auto k0 = k_interp_rs_ld<NT0>;
+  int wpb2 = 0, occ2 = 0, wpb0 = 0, occ0 = 0;
+  if (!pick_wpb(k2, L2, lim, wpb2, occ2) || !pick_wpb(k0, L0, lim, wpb0, occ0)) return FLINTS_ELIMIT;
+  const int lds2 = L2.tab_bytes + wpb2 * L2.wave_bytes;
+  const int lds0 = L0.tab_bytes + wpb0 * L0.wave_bytes;
+  const int64_t chunk = std::min<int64_t>(TQU_CHUNK, (n + 3) & ~int64_t(3));
+  int *stn = nullptr;
+  if (hipMallocAsync((void **)&stn, (size_t)chunk * K * sizeof(int), s) != hipSuccess) {
+    (void)hipGetLastError();   // no buffer: one searching pass per plan instead
+    const int rc = launch_interpolate(p0, map0, theta, phi, n, out0, var0, s);
+    return rc != FLINTS_OK ? rc : launch_interpolate(p2, map2, theta, phi, n, out2, var2, s);
+  }
+  hipFuncSetAttribute((const void *)k2, hipFuncAttributeMaxDynamicSharedMemorySize, lds2);
+  hipFuncSetAttribute((const void *)k0, hipFuncAttributeMaxDynamicSharedMemorySize, lds0);
+  for (int64_t s0 = 0; s0 < n; s0 += chunk) {
+    const int64_t s1 = std::min(n, s0 + chunk);
+    const int64_t g2 = (s1 - s0 + PPW2 - 1) / PPW2, g0 = (s1 - s0 + 3) / 4;
+    const int64_t b2 = std::max<int64_t>(std::min<int64_t>((g2 + wpb2 - 1) / wpb2, (int64_t)lim.ncu * occ2), 1);
+    const int64_t b0 = std::max<int64_t>(std::min<int64_t>((g0 + wpb0 - 1) / wpb0, (int64_t)lim.ncu * occ0), 1);
+    hipLaunchKernelGGL(k2, dim3((unsigned)b2), dim3(wpb2 * WAVE), lds2, s, p2->d, map2, theta, phi, n,
+                       out2, var2, L2, stn, s0, s1);
+    hipLaunchKernelGGL(k0, dim3((unsigned)b0), dim3(wpb0 * WAVE), lds0, s, p0->d, map0, theta, phi, n,
+                       out0, var0, L0, (const int *)stn, s0, s1);
+  }
+  (void)hipFreeAsync(stn, s);
+  auto esc2 = [] {
+    if constexpr (T2 != 0) return k_fixup<TileEngine<T2, 2>, 2>;
+    else return k_fixup<RowGroupEngine<NT2, 2>, 2>;
+  }();
+  auto esc0 = k_fixup<RowGroupEngine<NT0, 0>, 0>;
+  const int64_t nch = (n + WAVE - 1) / WAVE;
+  const int64_t e2 = std::max<int64_t>(std::min<int64_t>((nch + wpb2 - 1) / wpb2, (int64_t)lim.ncu * 4), 1);
+  const int64_t e0 = std::max<int64_t>(std::min<int64_t>((nch + wpb0 - 1) / wpb0, (int64_t)lim.ncu * 4), 1);
+  hipFuncSetAttribute((const void *)esc2, hipFuncAttributeMaxDynamicSharedMemorySize, lds2);
+  hipLaunchKernelGGL(esc2, dim3((unsigned)e2), dim3(wpb2 * WAVE), lds2, s, p2->d, map2, theta, phi, n,
+                     out2, var2, L2);
+  hipFuncSetAttribute((const void *)esc0, hipFuncAttributeMaxDynamicSharedMemorySize, lds0);
+  hipLaunchKernelGGL(esc0, dim3((unsigned)e0), dim3(wpb0 * WAVE), lds0, s, p0->d, map0, theta, phi, n,
+                     out0, var0, L0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("T + Q/U interpolation launch failed: ") + hipGetErrorString(e));
+    return FLINTS_EDEVICE;
+  }
+  return FLINTS_OK;
+}
+
+// True when the shared-stencil path applies: FP64 plans with paper variance (or no
+// variance requested) and one stencil for both, i.e. equal N_side, K and search
+// radii, with K <= 32.
+bool tqu_fusable(const Plan *p0, const Plan *p2, const double *var0, const double *var2) {
+  const PlanDev &a = p0->d, &b = p2->d;
+  const bool mse0 = a.var_kind == FLINTS_VAR_MSE && var0 != nullptr;
+  const bool mse2 = b.var_kind == FLINTS_VAR_MSE && var2 != nullptr;
+  return a.precision == FLINTS_FP64 && b.precision == FLINTS_FP64 && !mse0 && !mse2 &&
+         a.nside == b.nside && a.K == b.K && a.K <= 32 && a.r0 == b.r0 && a.rcap == b.rcap;
+}
+
+int launch_interpolate_tqu(const Plan *p0, const Plan *p2, const double *map0, const double *map2,
+                           const double *theta, const double *phi, int64_t n, double *out0,
+                           double *var0, double *out2, double *var2, hipStream_t s) {
+  if (n == 0) return FLINTS_OK;
+  if (!tqu_fusable(p0, p2, var0, var2)) {
+    const int rc = launch_interpolate(p0, map0, theta, phi, n, out0, var0, s);
+    if (rc != FLINTS_OK) return rc;
+    return launch_interpolate(p2, map2, theta, phi, n, out2, var2, s);
+  }
+  const int K = p0->d.K;
+  if (K <= 8)
+    return launch_tqu_t<1, 1, 0>(p0, p2, map0, map2, theta, phi, n, out0, var0, out2, var2, s);
+  if (K <= 16)
+    return launch_tqu_t<1, 2, 0>(p0, p2, map0, map2, theta, phi, n, out0, var0, out2, var2, s);
+  if (K <= 24)
+    return launch_tqu_t<2, 0, 3>(p0, p2, map0, map2, theta, phi, n, out0, var0, out2, var2, s);
+  return launch_tqu_t<2, 0, 4>(p0, p2, map0, map2, theta, phi, n, out0, var0, out2, var2, s);
 }
 
 int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_t n, int64_t *idx,

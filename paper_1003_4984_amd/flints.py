@@ -60,6 +60,7 @@ class _BatchInfo(ctypes.Structure):
 BATCH_AUTOTUNE = 1
 
 EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
+           "flints_interpolate_tqu", "flints_tqu_fused",
            "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
            "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error",
            "flints_batch_create", "flints_batch_run", "flints_batch_capture", "flints_batch_info",
@@ -84,6 +85,10 @@ def load_library(path=LIB_PATH):
     lib.flints_plan_ex.restype = vp
     lib.flints_interpolate.argtypes = [vp, dp, dp, dp, i64, dp, dp, vp]
     lib.flints_interpolate.restype = c_int
+    lib.flints_interpolate_tqu.argtypes = [vp, vp, dp, dp, dp, dp, i64, dp, dp, dp, dp, vp]
+    lib.flints_interpolate_tqu.restype = c_int
+    lib.flints_tqu_fused.argtypes = [vp, vp, c_int, c_int]
+    lib.flints_tqu_fused.restype = c_int
     lib.flints_stencil.argtypes = [vp, dp, dp, i64, dp, vp]
     lib.flints_stencil.restype = c_int
     lib.flints_table_eval.argtypes = [vp, dp, i64, dp, vp]
@@ -215,6 +220,49 @@ def interpolate(plan, map_, theta, phi, out=None, var=None, want_var=True, strea
                                 _ptr(var, "var", torch.float64), _stream(stream))
     _check(lib, rc, "flints_interpolate")
     return out, var
+
+
+def interpolate_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, out_t=None, var_t=None, out_qu=None,
+                    var_qu=None, want_var=True, stream=None):
+    """T and Q/U at the same targets with one stencil search per target
+    (flints_interpolate_tqu).  Returns (out_t, var_t, out_qu, var_qu)."""
+    import torch
+    n = theta.numel()
+    if phi.numel() != n:
+        raise FlintsError("theta and phi must have the same length")
+    if plan_t.nfield != 1 or plan_qu.nfield != 2:
+        raise FlintsError("plan_t must be spin 0 and plan_qu spin 2")
+    if map_t.numel() != plan_t.npix or map_qu.numel() != 2 * plan_qu.npix:
+        raise FlintsError("map_t must hold npix values and map_qu 2 npix")
+    dev = theta.device
+    if out_t is None:
+        out_t = torch.empty(n, dtype=torch.float64, device=dev)
+    if out_qu is None:
+        out_qu = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    if want_var and var_t is None:
+        var_t = torch.empty(n, dtype=torch.float64, device=dev)
+    if want_var and var_qu is None:
+        var_qu = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    if (out_t.numel() != n or out_qu.numel() != 2 * n or (var_t is not None and var_t.numel() != n)
+            or (var_qu is not None and var_qu.numel() != 2 * n)):
+        raise FlintsError("outputs have the wrong size")
+    lib = plan_t._lib
+    rc = lib.flints_interpolate_tqu(plan_t.handle, plan_qu.handle, _ptr(map_t, "map_t", torch.float64),
+                                    _ptr(map_qu, "map_qu", torch.float64),
+                                    _ptr(theta, "theta", torch.float64), _ptr(phi, "phi", torch.float64),
+                                    int(n), _ptr(out_t, "out_t", torch.float64),
+                                    _ptr(var_t, "var_t", torch.float64),
+                                    _ptr(out_qu, "out_qu", torch.float64),
+                                    _ptr(var_qu, "var_qu", torch.float64), _stream(stream))
+    _check(lib, rc, "flints_interpolate_tqu")
+    return out_t, var_t, out_qu, var_qu
+
+
+def tqu_fused(plan_t, plan_qu, with_var=True):
+    """True if interpolate_tqu shares one search between the two plans."""
+    rc = plan_t._lib.flints_tqu_fused(plan_t.handle, plan_qu.handle, int(with_var), int(with_var))
+    _check(plan_t._lib, min(rc, 0), "flints_tqu_fused")
+    return rc == 1
 
 
 def stencil(plan, theta, phi, stream=None):

@@ -1,0 +1,156 @@
+"""Fused T + Q/U (flints_interpolate_tqu): one stencil search per target for a
+spin-0 and a spin-2 plan of equal N_side and K.  Outputs, variances and plan
+counters must equal two separate flints_interpolate calls bit for bit, for
+each system-size class of the fused kernel (spin-2 rows on row groups or
+tiles), with ragged target counts, invalid targets and nugget escalation in
+the fix-up pass; plan pairs the fused kernel does not cover run as two calls."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1003_4984_amd as fl
+from oracle import kriging
+from workload import spectra, synth, seeds
+
+from _gpu_helpers import dev, gpu_stencil, reconcile_stencils, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _maps(nside, lmax, seed, cl_tt=None, cl_ee=None):
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    cl_tt = tt if cl_tt is None else cl_tt
+    cl_ee = ee if cl_ee is None else cl_ee
+    r = seeds.rng(41, seed, 0)
+    t = synth.synth(synth.draw_alm(r, cl_tt, lmax), 0, nside)
+    q, u = synth.synth(-synth.draw_alm(r, cl_ee, lmax), 2, nside)
+    return dev(t.numpy()), dev(torch.cat([q, u]).numpy()), cl_tt, cl_ee
+
+
+def _targets(n, seed, bad=False):
+    rng = seeds.rng(41, seed, 3)
+    th = np.arccos(rng.uniform(-1, 1, n))
+    ph = rng.uniform(-7.0, 14.0, n)
+    if bad and n >= 8:
+        th[1], th[5], ph[6] = np.nan, np.pi + 1e-3, np.inf
+        th[2], th[3] = 0.0, np.pi          # the poles are valid
+    return dev(th), dev(ph)
+
+
+def _separate(p0, p2, mt, mqu, th, ph, want_var=True):
+    o0, v0 = fl.interpolate(p0, mt, th, ph, want_var=want_var)
+    o2, v2 = fl.interpolate(p2, mqu, th, ph, want_var=want_var)
+    torch.cuda.synchronize()
+    return o0, v0, o2, v2
+
+
+def _check_fused_equals_separate(p0, p2, mt, mqu, th, ph, want_var=True, fused=True):
+    assert fl.tqu_fused(p0, p2, with_var=want_var) == fused
+    for p in (p0, p2):
+        p.reset_stats()
+    ref = _separate(p0, p2, mt, mqu, th, ph, want_var)
+    st_ref = (p0.stats(), p2.stats())
+    for p in (p0, p2):
+        p.reset_stats()
+    # outputs preset to garbage, so every element must be written
+    n = th.numel()
+    outs = [torch.full((k * n,), -5.0, dtype=torch.float64, device="cuda") for k in (1, 1, 2, 2)]
+    if not want_var:
+        outs[1] = outs[3] = None
+    got = fl.interpolate_tqu(p0, p2, mt, mqu, th, ph, out_t=outs[0], var_t=outs[1], out_qu=outs[2],
+                             var_qu=outs[3], want_var=want_var)
+    torch.cuda.synchronize()
+    for name, a, b in zip(("T", "var T", "QU", "var QU"), got, ref):
+        if b is None:
+            assert a is None
+            continue
+        assert torch.equal(a.isnan(), b.isnan()), f"{name}: NaN pattern differs"
+        assert torch.equal(torch.nan_to_num(a), torch.nan_to_num(b)), f"{name}: differs from separate calls"
+    assert (p0.stats(), p2.stats()) == st_ref
+    return got
+
+
+# K: 8 (spin-2 rows on one row group), 12 (two), 24 (tiles of 3), 32 (tiles of 4)
+@pytest.mark.parametrize("K,n", [(8, 1001), (12, 4003), (24, 2001), (32, 3002)])
+def test_fused_equals_separate(gpu_ok, K, n):
+    nside, lmax = 64, 128
+    mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, K)
+    p0 = fl.Plan(nside, lmax, cl_tt, K, 0)
+    p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, 0.1 * cl_ee]), K, 2)
+    th, ph = _targets(n, K, bad=True)
+    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph)
+    assert p0.stats()["bad_inputs"] == 3 and p2.stats()["bad_inputs"] == 3
+    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph, want_var=False)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5])
+def test_fused_tiny(gpu_ok, n):
+    nside, lmax, K = 16, 32, 32
+    mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 7)
+    p0 = fl.Plan(nside, lmax, cl_tt, K, 0)
+    p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, cl_ee]), K, 2, spin2_mode=fl.S2_PAPER)
+    th, ph = _targets(n, 100 + n)
+    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph)
+
+
+def test_fused_nugget_escalation(gpu_ok):
+    """Single-l spectra with the paper-literal nugget policy: S is singular
+    (rank 2l+1 < K for T, at most 2(2l+1) < 2K for Q/U), so the fix-up passes
+    escalate the nugget."""
+    nside, K, L = 16, 20, 3
+    cl = np.zeros(L + 1)
+    cl[L] = 1.0
+    mt, mqu, _, _ = _maps(nside, L, 9, cl_tt=cl, cl_ee=cl)
+    p0 = fl.Plan(nside, L, cl, K, 0, nugget=fl.NUG_ON_FAILURE)
+    p2 = fl.Plan(nside, L, np.concatenate([cl, np.zeros(L + 1)]), K, 2, nugget=fl.NUG_ON_FAILURE)
+    th, ph = _targets(300, 9)
+    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph)
+    assert p0.stats()["nugget_escalations"] > 0
+
+
+def test_unfused_pairs_run_as_two_calls(gpu_ok):
+    nside, lmax, K = 32, 64, 16
+    mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 11)
+    th, ph = _targets(777, 11)
+    p0 = fl.Plan(nside, lmax, cl_tt, K, 0, precision=fl.FP32_IR)
+    p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, cl_ee]), K, 2)
+    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph, fused=False)
+    p0m = fl.Plan(nside, lmax, cl_tt, K, 0, var_kind=fl.VAR_MSE)
+    _check_fused_equals_separate(p0m, p2, mt, mqu, th, ph, fused=False)
+    # MSE variance not requested: the fused kernel applies
+    _check_fused_equals_separate(p0m, p2, mt, mqu, th, ph, want_var=False, fused=True)
+
+
+def test_fused_rejects_mismatched_plans(gpu_ok):
+    nside, lmax = 32, 64
+    mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 12)
+    th, ph = _targets(10, 12)
+    p0 = fl.Plan(nside, lmax, cl_tt, 16, 0)
+    p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, cl_ee]), 24, 2)
+    with pytest.raises(fl.FlintsError):
+        fl.interpolate_tqu(p0, p2, mt, mqu, th, ph)
+    p2b = fl.Plan(nside, lmax, np.concatenate([cl_ee, cl_ee]), 16, 2)
+    with pytest.raises(fl.FlintsError):
+        fl.interpolate_tqu(p2b, p0, mqu, mt, th, ph)
+
+
+def test_fused_against_oracle(gpu_ok):
+    nside, lmax, K = 32, 64, 24
+    mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 13)
+    p0 = fl.Plan(nside, lmax, cl_tt, K, 0)
+    p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, 0.1 * cl_ee]), K, 2)
+    th, ph = _targets(400, 13)
+    o0, v0, o2, v2 = fl.interpolate_tqu(p0, p2, mt, mqu, th, ph)
+    torch.cuda.synchronize()
+    thn, phn = th.cpu().numpy(), ph.cpu().numpy()
+    g = gpu_stencil(p0, thn, phn)
+    reconcile_stencils(nside, thn, phn, g, kriging.stencils(nside, thn, phn, K))
+    npix = 12 * nside * nside
+    m2 = mqu.cpu().numpy()
+    vo, varo, _ = kriging.interpolate(nside, cl_tt, K, 0, mt.cpu().numpy(), thn, phn, stencil_idx=g)
+    compare(o0.cpu().numpy(), v0.cpu().numpy(), vo, varo, 1e-8, 1e-4, 1e-9 * p0.info()["sigma2"])
+    vo, varo, _ = kriging.interpolate(nside, (cl_ee, 0.1 * cl_ee), K, 2, (m2[:npix], m2[npix:]), thn, phn,
+                                      stencil_idx=g)
+    n = th.numel()
+    compare(o2.cpu().numpy().reshape(2, n).T, v2.cpu().numpy().reshape(2, n).T, vo, varo, 1e-8, 1e-4,
+            1e-9 * p2.info()["sigma2"])
