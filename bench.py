@@ -9,7 +9,8 @@ before timing and stay resident in HBM.
 
 Prints ONE JSON line.  `value` counts interpolated field samples (T, Q and U
 separately) per second.  `roofline` is the dominant kernel's algorithmic FP64
-flop rate (the fused T+Q/U launch, or with --tqu separate the spin-2 launch),
+flop rate (the T+Q/U call with shared stencils, or with --tqu separate the
+spin-2 launch),
 timed with HIP events on the launch stream, against the MI355X FP64 vector
 peak.  `cpu_baseline` is the FP64 CPU
 oracle on a bounded sample of the same workload, which also serves as a
@@ -45,8 +46,8 @@ def flops_spin2(K):
     return 16.0 / 3.0 * K ** 3 + 16 * K ** 2 + 60 * (K * (K + 1) / 2 + K)
 
 
-# Counter summaries of the dominant launch per T+Q+U mode (fused: one launch
-# for all three fields; separate: the spin-2 launch).
+# Counter summaries of the dominant work per T+Q+U mode (fused: all kernels of
+# the shared-stencil T+Q/U call; separate: the spin-2 launch).
 TRAFFIC_FILES = {
     "fused": os.path.join(ROOT, "profiles", "traffic_interp_tqu_nside4096_K32.md"),
     "separate": os.path.join(ROOT, "profiles", "traffic_interp_tile_nside4096_K32.md"),
@@ -171,8 +172,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tqu", default="fused", choices=["fused", "separate"],
-                    help="T and Q/U in one launch sharing the stencil search (fused), or one "
-                         "launch per plan (separate)")
+                    help="T and Q/U in one call sharing the stencil search (fused), or one "
+                         "call per plan (separate)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy of "
                          "known size that calibrates HBM traffic counters)")
@@ -249,9 +250,10 @@ def main():
     if fused:
         fpp = flops_spin0(K) + flops_spin2(K)
         achieved = fpp * n / t_spin0.mean() / 1e12
-        kname = "fused T+Q/U launch (k_interp_tqu<2,0,4> + two fix-up scans)"
+        kname = ("T+Q/U call with shared stencils (12 x k_interp_tile_st<4> + 12 x k_interp_rs_ld<2> "
+                 "+ two fix-up scans)")
         kernel_s = {"tqu": float(t_spin0.mean())}
-        tunit = "HBM bytes per fused T+Q/U launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)"
+        tunit = "HBM bytes per T+Q/U call (rocprofv3 FETCH_SIZE + WRITE_SIZE, all its kernels)"
     else:
         fpp = flops_spin2(K)
         achieved = fpp * n / t_spin2.mean() / 1e12
