@@ -256,11 +256,11 @@ typedef struct {
   int64_t points;            /* total targets */
   int fused_jobs;            /* jobs on the persistent launches */
   int classes;               /* persistent launch groups used per run */
-  /* per launch group g = 3 * engine + bucket: engine by rows n <= 16, 32, 48,
-   * 64; bucket by correlation-table size <= 16 KB, <= 48 KB, larger */
-  int tiles[12];
-  int tile_points[12];       /* targets per tile (0 = group unused) */
-  int waves_per_block[12];
+  /* per launch group g = 6 * engine + bucket: engine by rows n <= 16, 32, 48,
+   * 64; bucket by correlation-table size <= 16, 32, 48, 64, 96 KB, larger */
+  int tiles[24];
+  int tile_points[24];       /* targets per tile (0 = group unused) */
+  int waves_per_block[24];
   int captured;              /* 1 if runs replay a graph */
 } flints_batch_info_t;
 

@@ -53,8 +53,8 @@ class _Job(ctypes.Structure):
 
 class _BatchInfo(ctypes.Structure):
     _fields_ = [("njobs", ctypes.c_int), ("points", ctypes.c_int64), ("fused_jobs", ctypes.c_int),
-                ("classes", ctypes.c_int), ("tiles", ctypes.c_int * 12), ("tile_points", ctypes.c_int * 12),
-                ("waves_per_block", ctypes.c_int * 12), ("captured", ctypes.c_int)]
+                ("classes", ctypes.c_int), ("tiles", ctypes.c_int * 24), ("tile_points", ctypes.c_int * 24),
+                ("waves_per_block", ctypes.c_int * 24), ("captured", ctypes.c_int)]
 
 
 BATCH_AUTOTUNE = 1
