@@ -7,8 +7,10 @@ waiting requests first-come first-served while the HBM they need (outputs,
 variances, maps, targets and any new plan's table) fits a budget and a launch slot is free;
 groups the requests admitted at one step into one batched launch
 (flints_batch_*) on the next free stream, so work of different requests
-overlaps on the device; and releases a request's memory when its completion
-event has fired.  Latency is completion minus arrival; the report gives p50
+overlaps on the device -- except that a T+Q+U request runs through
+flints_interpolate_tqu on that stream (one K-nearest search per target serves
+both its plans); and releases a request's memory when its completion event
+has fired.  Latency is completion minus arrival; the report gives p50
 and p99 next to throughput in samples per second.
 
 The scheduling logic is independent of the device: `Server` drives an
@@ -168,14 +170,17 @@ def report(done, wall):
 
 class DeviceExecutor:
     """FLINTS executor: one flints batch per admitted group, on `slots` streams
-    of default priority; completion via a recorded event."""
+    of default priority; completion via a recorded event.  With `tqu_shared`,
+    T+Q+U requests run through interpolate_tqu (shared stencil search) on the
+    group's stream instead of as two batch jobs."""
 
-    def __init__(self, plans, slots):
+    def __init__(self, plans, slots, tqu_shared=True):
         import torch
         import paper_1003_4984_amd as fl
         self.fl, self.torch = fl, torch
         self.plans = plans
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.tqu_shared = tqu_shared
 
     def jobs_for(self, r):
         torch, fl = self.torch, self.fl
@@ -193,14 +198,28 @@ class DeviceExecutor:
             jobs.append((p2, r.maps["QU"], r.theta, r.phi, o2, v2))
         return jobs
 
+    def run_tqu(self, r, s):
+        torch, fl = self.torch, self.fl
+        p0 = self.plans.get(r.nside, r.lmax, r.K, 0, r.cl_tt)
+        p2 = self.plans.get(r.nside, r.lmax, r.K, 2, np.concatenate([r.cl_ee, r.cl_bb]))
+        o, v, o2, v2 = fl.interpolate_tqu(p0, p2, r.maps["T"], r.maps["QU"], r.theta, r.phi, stream=s)
+        r.out["T"] = (o, v)
+        r.out["QU"] = (o2, v2)
+
     def launch(self, group, slot):
         torch = self.torch
         s = self.streams[slot]
-        jobs = [j for r in group for j in self.jobs_for(r)]
+        shared = [r for r in group if self.tqu_shared and r.fields == "TQU"]
+        ids = {id(r) for r in shared}
+        jobs = [j for r in group if id(r) not in ids for j in self.jobs_for(r)]
         # inputs were written on the default stream; order this stream after it
         s.wait_stream(torch.cuda.current_stream())
-        b = self.fl.Batch(jobs)
-        b.run(s)
+        b = None
+        if jobs:
+            b = self.fl.Batch(jobs)
+            b.run(s)
+        for r in shared:
+            self.run_tqu(r, s)
         ev = torch.cuda.Event()
         ev.record(s)
         return (ev, b, jobs)
@@ -208,7 +227,8 @@ class DeviceExecutor:
     def done(self, token):
         ev, b, jobs = token
         if ev.query():
-            b.close()
+            if b is not None:
+                b.close()
             return True
         return False
 
@@ -253,6 +273,8 @@ def main():
     ap.add_argument("--nsides", default="256,1024,2048")
     ap.add_argument("--weights", default="0.4,0.3,0.2")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-tqu-shared", action="store_true",
+                    help="run T+Q+U requests as two batch jobs instead of interpolate_tqu")
     args = ap.parse_args()
     import torch
     import paper_1003_4984_amd as fl
@@ -261,7 +283,7 @@ def main():
     reqs = make_requests(args.requests, args.rate, args.seed, nsides, weights)
     torch.cuda.synchronize()
     plans = PlanCache(lambda nside, lmax, cl, K, spin: fl.Plan(nside, lmax, cl, K, spin))
-    ex = DeviceExecutor(plans, args.slots)
+    ex = DeviceExecutor(plans, args.slots, tqu_shared=not args.no_tqu_shared)
     srv = Server(ex, args.budget_gb * 2 ** 30, args.slots, plans,
                  max_group_samples=int(args.group_msamples * 1e6))
     t0 = time.perf_counter()
@@ -269,7 +291,7 @@ def main():
     torch.cuda.synchronize()
     rep = report(done, time.perf_counter() - t0)
     rep.update({"rate_per_s": args.rate, "slots": args.slots, "plans_cached": len(plans),
-                "group_msamples": args.group_msamples,
+                "group_msamples": args.group_msamples, "tqu_shared": not args.no_tqu_shared,
                 "peak_admitted_bytes": srv.peak, "nsides": list(nsides), "K": 32})
     print(json.dumps(rep), flush=True)
 

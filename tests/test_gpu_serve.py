@@ -1,6 +1,7 @@
 """Serving on the device: requests of several N_side arriving faster than they
-are served overlap on two streams in batched launches; every result must equal
-the same request computed alone (bit for bit), and p50/p99 are reported."""
+are served overlap on two streams in batched launches (T+Q+U requests through
+the shared-stencil call, or as two batch jobs); every result must equal the
+same request computed alone (bit for bit), and p50/p99 are reported."""
 import pytest
 import torch
 
@@ -10,12 +11,13 @@ from paper_1003_4984_amd.serve import DeviceExecutor, PlanCache, Server, make_re
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_alone(gpu_ok):
+@pytest.mark.parametrize("tqu_shared", [True, False])
+def test_served_results_equal_alone(gpu_ok, tqu_shared):
     reqs = make_requests(10, rate=2000.0, seed=1, nsides=(16, 32, 64), weights=(0.4, 0.3, 0.3),
                          tqu_frac=0.5, K=16, device="cuda")
     torch.cuda.synchronize()
     plans = PlanCache(lambda nside, lmax, cl, K, spin: fl.Plan(nside, lmax, cl, K, spin))
-    ex = DeviceExecutor(plans, slots=2)
+    ex = DeviceExecutor(plans, slots=2, tqu_shared=tqu_shared)
     srv = Server(ex, hbm_budget=2 ** 30, slots=2, plans=plans)
     done = srv.run(reqs)
     torch.cuda.synchronize()
