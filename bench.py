@@ -46,10 +46,10 @@ def flops_spin2(K):
     return 16.0 / 3.0 * K ** 3 + 16 * K ** 2 + 60 * (K * (K + 1) / 2 + K)
 
 
-# Counter summaries of the dominant work per T+Q+U mode (fused: all kernels of
+# Counter summaries of the dominant work per T+Q+U mode (shared: all kernels of
 # the shared-stencil T+Q/U call; separate: the spin-2 launch).
 TRAFFIC_FILES = {
-    "fused": os.path.join(ROOT, "profiles", "traffic_interp_tqu_nside4096_K32.md"),
+    "shared": os.path.join(ROOT, "profiles", "traffic_interp_tqu_nside4096_K32.md"),
     "separate": os.path.join(ROOT, "profiles", "traffic_interp_tile_nside4096_K32.md"),
 }
 
@@ -81,7 +81,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, mode="fused"):
+def measured_traffic(workload, mode="shared"):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if that summary
     is for other kernel sources or another workload."""
@@ -179,8 +179,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32ir"])
     ap.add_argument("--cpu-sample", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tqu", default="fused", choices=["fused", "separate"],
-                    help="T and Q/U in one call sharing the stencil search (fused), or one "
+    ap.add_argument("--tqu", default="shared", choices=["shared", "separate"],
+                    help="T and Q/U in one call sharing the stencil search (shared), or one "
                          "call per plan (separate)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy of "
@@ -216,12 +216,12 @@ def main():
     var_qu = torch.empty(2 * n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    fused = args.tqu == "fused"
+    shared = args.tqu == "shared"
 
     def step(ev=None):
         if ev:
             ev[0].record(stream)
-        if fused:
+        if shared:
             fl.interpolate_tqu(p0, p2, inp["T"], inp["QU"], inp["theta"], inp["phi"], out_t=out_t,
                                var_t=var_t, out_qu=out_qu, var_qu=var_qu, stream=stream)
             if ev:
@@ -255,7 +255,7 @@ def main():
     st0, st2 = p0.stats(), p2.stats()
 
     K = shape["K"]
-    if fused:
+    if shared:
         fpp = flops_spin0(K) + flops_spin2(K)
         achieved = fpp * n / t_spin0.mean() / 1e12
         kname = ("T+Q/U call with shared stencils (12 x k_interp_tile_st<4> + 12 x k_interp_rs_ld<2> "

@@ -141,7 +141,7 @@ int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
  *   var_t, var_qu  device, nullable, same layouts as the outputs.
  * The search is shared when both plans are FLINTS_FP64 with paper variance
  * (or their variance is not requested) and their search radii agree (see
- * flints_tqu_fused); other plan pairs, or a failed allocation of the stencil
+ * flints_tqu_shared); other plan pairs, or a failed allocation of the stencil
  * buffer, run as the two separate calls on the same stream.  The buffer holds
  * K ints per target for chunks of up to 2^24 targets (2 GiB at K = 32) and is
  * allocated and freed on the stream (hipMallocAsync / hipFreeAsync).  Invalid
@@ -156,7 +156,7 @@ int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const vo
 /* 1 if flints_interpolate_tqu shares the stencil search between these plans
  * (with_var_*: whether variances will be requested), 0 if it runs two
  * separate calls, < 0 on error.  Host-only; launches nothing. */
-int flints_tqu_fused(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu);
+int flints_tqu_shared(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu);
 
 /*
  * Stencil of each target: the K nearest RING pixels, ascending distance, ties to

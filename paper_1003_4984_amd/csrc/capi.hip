@@ -182,11 +182,11 @@ int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const vo
                                 (hipStream_t)stream);
 }
 
-int flints_tqu_fused(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu) {
+int flints_tqu_shared(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu) {
   g_last_error.clear();
   if (!plan_t || !plan_qu) { set_error("plans must be non-NULL"); return FLINTS_EINVAL; }
   const double some = 0.0;   // stands for a variance array; only its presence matters
-  return tqu_fusable(as_plan(plan_t), as_plan(plan_qu), with_var_t ? &some : nullptr,
+  return tqu_shareable(as_plan(plan_t), as_plan(plan_qu), with_var_t ? &some : nullptr,
                      with_var_qu ? &some : nullptr) ? 1 : 0;
 }
 

@@ -528,7 +528,7 @@ static int launch_tqu_t(const Plan *p0, const Plan *p2, const double *map0, cons
 // True when the shared-stencil path applies: FP64 plans with paper variance (or no
 // variance requested) and one stencil for both, i.e. equal N_side, K and search
 // radii, with K <= 32.
-bool tqu_fusable(const Plan *p0, const Plan *p2, const double *var0, const double *var2) {
+bool tqu_shareable(const Plan *p0, const Plan *p2, const double *var0, const double *var2) {
   const PlanDev &a = p0->d, &b = p2->d;
   const bool mse0 = a.var_kind == FLINTS_VAR_MSE && var0 != nullptr;
   const bool mse2 = b.var_kind == FLINTS_VAR_MSE && var2 != nullptr;
@@ -540,7 +540,7 @@ int launch_interpolate_tqu(const Plan *p0, const Plan *p2, const double *map0, c
                            const double *theta, const double *phi, int64_t n, double *out0,
                            double *var0, double *out2, double *var2, hipStream_t s) {
   if (n == 0) return FLINTS_OK;
-  if (!tqu_fusable(p0, p2, var0, var2)) {
+  if (!tqu_shareable(p0, p2, var0, var2)) {
     const int rc = launch_interpolate(p0, map0, theta, phi, n, out0, var0, s);
     if (rc != FLINTS_OK) return rc;
     return launch_interpolate(p2, map2, theta, phi, n, out2, var2, s);

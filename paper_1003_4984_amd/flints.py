@@ -60,7 +60,7 @@ class _BatchInfo(ctypes.Structure):
 BATCH_AUTOTUNE = 1
 
 EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
-           "flints_interpolate_tqu", "flints_tqu_fused",
+           "flints_interpolate_tqu", "flints_tqu_shared",
            "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
            "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error",
            "flints_batch_create", "flints_batch_run", "flints_batch_capture", "flints_batch_info",
@@ -87,8 +87,8 @@ def load_library(path=LIB_PATH):
     lib.flints_interpolate.restype = c_int
     lib.flints_interpolate_tqu.argtypes = [vp, vp, dp, dp, dp, dp, i64, dp, dp, dp, dp, vp]
     lib.flints_interpolate_tqu.restype = c_int
-    lib.flints_tqu_fused.argtypes = [vp, vp, c_int, c_int]
-    lib.flints_tqu_fused.restype = c_int
+    lib.flints_tqu_shared.argtypes = [vp, vp, c_int, c_int]
+    lib.flints_tqu_shared.restype = c_int
     lib.flints_stencil.argtypes = [vp, dp, dp, i64, dp, vp]
     lib.flints_stencil.restype = c_int
     lib.flints_table_eval.argtypes = [vp, dp, i64, dp, vp]
@@ -258,10 +258,10 @@ def interpolate_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, out_t=None, var_
     return out_t, var_t, out_qu, var_qu
 
 
-def tqu_fused(plan_t, plan_qu, with_var=True):
+def tqu_shared(plan_t, plan_qu, with_var=True):
     """True if interpolate_tqu shares one search between the two plans."""
-    rc = plan_t._lib.flints_tqu_fused(plan_t.handle, plan_qu.handle, int(with_var), int(with_var))
-    _check(plan_t._lib, min(rc, 0), "flints_tqu_fused")
+    rc = plan_t._lib.flints_tqu_shared(plan_t.handle, plan_qu.handle, int(with_var), int(with_var))
+    _check(plan_t._lib, min(rc, 0), "flints_tqu_shared")
     return rc == 1
 
 

@@ -1,9 +1,9 @@
-"""Fused T + Q/U (flints_interpolate_tqu): one stencil search per target for a
-spin-0 and a spin-2 plan of equal N_side and K.  Outputs, variances and plan
-counters must equal two separate flints_interpolate calls bit for bit, for
-each system-size class of the fused kernel (spin-2 rows on row groups or
+"""T + Q/U with shared stencils (flints_interpolate_tqu): one stencil search per
+target for a spin-0 and a spin-2 plan of equal N_side and K.  Outputs,
+variances and plan counters must equal two separate flints_interpolate calls
+bit for bit, for each system-size class of the spin-2 pass (row groups or
 tiles), with ragged target counts, invalid targets and nugget escalation in
-the fix-up pass; plan pairs the fused kernel does not cover run as two calls."""
+the fix-up pass; plan pairs the shared path does not cover run as two calls."""
 import numpy as np
 import pytest
 import torch
@@ -44,8 +44,8 @@ def _separate(p0, p2, mt, mqu, th, ph, want_var=True):
     return o0, v0, o2, v2
 
 
-def _check_fused_equals_separate(p0, p2, mt, mqu, th, ph, want_var=True, fused=True):
-    assert fl.tqu_fused(p0, p2, with_var=want_var) == fused
+def _check_shared_equals_separate(p0, p2, mt, mqu, th, ph, want_var=True, shared=True):
+    assert fl.tqu_shared(p0, p2, with_var=want_var) == shared
     for p in (p0, p2):
         p.reset_stats()
     ref = _separate(p0, p2, mt, mqu, th, ph, want_var)
@@ -72,28 +72,28 @@ def _check_fused_equals_separate(p0, p2, mt, mqu, th, ph, want_var=True, fused=T
 
 # K: 8 (spin-2 rows on one row group), 12 (two), 24 (tiles of 3), 32 (tiles of 4)
 @pytest.mark.parametrize("K,n", [(8, 1001), (12, 4003), (24, 2001), (32, 3002)])
-def test_fused_equals_separate(gpu_ok, K, n):
+def test_shared_equals_separate(gpu_ok, K, n):
     nside, lmax = 64, 128
     mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, K)
     p0 = fl.Plan(nside, lmax, cl_tt, K, 0)
     p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, 0.1 * cl_ee]), K, 2)
     th, ph = _targets(n, K, bad=True)
-    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph)
+    _check_shared_equals_separate(p0, p2, mt, mqu, th, ph)
     assert p0.stats()["bad_inputs"] == 3 and p2.stats()["bad_inputs"] == 3
-    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph, want_var=False)
+    _check_shared_equals_separate(p0, p2, mt, mqu, th, ph, want_var=False)
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 5])
-def test_fused_tiny(gpu_ok, n):
+def test_shared_tiny(gpu_ok, n):
     nside, lmax, K = 16, 32, 32
     mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 7)
     p0 = fl.Plan(nside, lmax, cl_tt, K, 0)
     p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, cl_ee]), K, 2, spin2_mode=fl.S2_PAPER)
     th, ph = _targets(n, 100 + n)
-    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph)
+    _check_shared_equals_separate(p0, p2, mt, mqu, th, ph)
 
 
-def test_fused_nugget_escalation(gpu_ok):
+def test_shared_nugget_escalation(gpu_ok):
     """Single-l spectra with the paper-literal nugget policy: S is singular
     (rank 2l+1 < K for T, at most 2(2l+1) < 2K for Q/U), so the fix-up passes
     escalate the nugget."""
@@ -104,24 +104,24 @@ def test_fused_nugget_escalation(gpu_ok):
     p0 = fl.Plan(nside, L, cl, K, 0, nugget=fl.NUG_ON_FAILURE)
     p2 = fl.Plan(nside, L, np.concatenate([cl, np.zeros(L + 1)]), K, 2, nugget=fl.NUG_ON_FAILURE)
     th, ph = _targets(300, 9)
-    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph)
+    _check_shared_equals_separate(p0, p2, mt, mqu, th, ph)
     assert p0.stats()["nugget_escalations"] > 0
 
 
-def test_unfused_pairs_run_as_two_calls(gpu_ok):
+def test_unshared_pairs_run_as_two_calls(gpu_ok):
     nside, lmax, K = 32, 64, 16
     mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 11)
     th, ph = _targets(777, 11)
     p0 = fl.Plan(nside, lmax, cl_tt, K, 0, precision=fl.FP32_IR)
     p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, cl_ee]), K, 2)
-    _check_fused_equals_separate(p0, p2, mt, mqu, th, ph, fused=False)
+    _check_shared_equals_separate(p0, p2, mt, mqu, th, ph, shared=False)
     p0m = fl.Plan(nside, lmax, cl_tt, K, 0, var_kind=fl.VAR_MSE)
-    _check_fused_equals_separate(p0m, p2, mt, mqu, th, ph, fused=False)
-    # MSE variance not requested: the fused kernel applies
-    _check_fused_equals_separate(p0m, p2, mt, mqu, th, ph, want_var=False, fused=True)
+    _check_shared_equals_separate(p0m, p2, mt, mqu, th, ph, shared=False)
+    # MSE variance not requested: the shared path applies
+    _check_shared_equals_separate(p0m, p2, mt, mqu, th, ph, want_var=False, shared=True)
 
 
-def test_fused_rejects_mismatched_plans(gpu_ok):
+def test_shared_rejects_mismatched_plans(gpu_ok):
     nside, lmax = 32, 64
     mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 12)
     th, ph = _targets(10, 12)
@@ -134,7 +134,7 @@ def test_fused_rejects_mismatched_plans(gpu_ok):
         fl.interpolate_tqu(p2b, p0, mqu, mt, th, ph)
 
 
-def test_fused_against_oracle(gpu_ok):
+def test_shared_against_oracle(gpu_ok):
     nside, lmax, K = 32, 64, 24
     mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 13)
     p0 = fl.Plan(nside, lmax, cl_tt, K, 0)
