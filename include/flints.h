@@ -257,7 +257,7 @@ typedef struct {
   int fused_jobs;            /* jobs on the persistent launches */
   int classes;               /* persistent launch groups used per run */
   /* per launch group g = 6 * engine + bucket: engine by rows n <= 16, 32, 48,
-   * 64; bucket by correlation-table size <= 16, 32, 48, 64, 96 KB, larger */
+   * 64; bucket by correlation-table size <= 16, 36, 57, 77, 98 KB, larger */
   int tiles[24];
   int tile_points[24];       /* targets per tile (0 = group unused) */
   int waves_per_block[24];

@@ -34,7 +34,7 @@ struct BatchTile {
 };
 
 constexpr int NENGINE = 4;   // row group NT = 1, 2; tile T = 3, 4
-constexpr int NTABB = 6;     // table-size buckets: <= 16, 32, 48, 64, 96 KB, larger
+constexpr int NTABB = 6;     // table-size buckets: <= 16, 36, 57, 77, 98 KB, larger
 constexpr int NCLASS = NENGINE * NTABB;   // launch groups, index NTABB * engine + bucket
 static_assert(sizeof(flints_batch_info_t::tiles) / sizeof(int) == NCLASS,
               "flints_batch_info_t holds one entry per launch group");
@@ -139,15 +139,15 @@ struct Batch {
 
 // Launch group of a job: engine by system size, and table-size bucket, so a
 // large table (few waves fit beside it in LDS) does not set the occupancy of
-// jobs with small ones.  The bucket edges follow the tile engine's per-wave
-// LDS (about 21 KB at n = 64): each step of 16 KB of table costs about one of
-// the seven waves a CU holds.
+// jobs with small ones.  The bucket edges are where the 64-row tile engine
+// (21,056 B of LDS per wave) loses a wave per CU: 7, 6, 5, 4 and 3 waves fit
+// beside tables of at most 16, 36, 57, 77 and 98 KB.
 static int job_class(const Plan *p) {
   if (p->d.precision != FLINTS_FP64 || p->d.var_kind != FLINTS_VAR_PAPER) return -1;
   const int n = p->d.n;
   const int e = n <= 16 ? 0 : n <= 32 ? 1 : n <= 48 ? 2 : 3;
   const int tb = p->d.ntab * p->d.nfun * 8;
-  static const int edge_kb[NTABB - 1] = {16, 32, 48, 64, 96};
+  static const int edge_kb[NTABB - 1] = {16, 36, 57, 77, 98};
   int k = 0;
   while (k < NTABB - 1 && tb > (edge_kb[k] << 10)) ++k;
   return NTABB * e + k;
