@@ -106,39 +106,3 @@ def test_exact_recovery_band_limited():
     s0 = np.sqrt(correlation.zeta(np.zeros(1), cl)[0][0])
     assert np.allclose(v, truth, atol=1e-3 * s0)
     assert np.all(var < 1e-6 * s0 ** 2)
-
-
-@pytest.mark.parametrize("spin", [0, 2])
-def test_calibration(spin):
-    """Sec. 3.2 (error normalised by the predicted deviation is N(0,1)):
-    truth by brute-force resummation of seeded tiny-l realisations."""
-    N, K, lmax = 4, 8, 6
-    ell = np.arange(lmax + 1, dtype=float)
-    cl = np.zeros(lmax + 1)
-    cl[1 if spin == 0 else 2:] = 1.0 / (ell[1 if spin == 0 else 2:] + 1.0) ** 2
-    rng = np.random.default_rng(10 + spin)
-    thp, php = healpix.pix2ang(N, np.arange(healpix.npix(N)))
-    zs = []
-    for rep in range(60):
-        alm = np.zeros((lmax + 1, lmax + 1), complex)
-        for l in range(lmax + 1):
-            alm[l, 0] = rng.normal() * np.sqrt(cl[l])
-            for mm in range(1, l + 1):
-                alm[l, mm] = (rng.normal() + 1j * rng.normal()) * np.sqrt(cl[l] / 2)
-        th, ph = np.arccos(rng.uniform(-1, 1, 40)), rng.uniform(0, 2 * np.pi, 40)
-        if spin == 0:
-            m = wigner.resum_spin0(alm, thp, php)
-            truth = wigner.resum_spin0(alm, th, ph)
-            v, var, _ = kriging.interpolate(N, cl, K, 0, m, th, ph, var_kind="mse")
-            zs.append((v - truth) / np.sqrt(var))
-        else:
-            q, u = wigner.resum_spin2(alm, 0 * alm, thp, php)
-            tq, tu = wigner.resum_spin2(alm, 0 * alm, th, ph)
-            v, var, _ = kriging.interpolate(N, (cl, 0 * cl), K, 2, (q, u), th, ph, var_kind="mse")
-            zs.append((v[:, 0] - tq) / np.sqrt(var[:, 0]))
-            zs.append((v[:, 1] - tu) / np.sqrt(var[:, 1]))
-    z = np.concatenate(zs)
-    # mean z^2 of n samples has sd sqrt(2/n) (points within a realisation are
-    # correlated, so allow a generous band)
-    assert 0.8 < np.mean(z ** 2) < 1.2
-    assert abs(np.mean(z)) < 0.15
