@@ -55,13 +55,13 @@ TRAFFIC_FILES = {
 
 
 # Sources outside the measured single-plan and T+Q/U kernels: the batched
-# launches and the machine-peak probe.
-NOT_MEASURED = ("batch.hip", "peaks.hip")
+# launches.
+NOT_MEASURED = ("batch.hip",)
 
 
 def kernel_source_hash():
     """sha256 of the sources of the measured kernels (all of csrc but the batch
-    and peak-probe files) with comments and blank space removed (a change of
+    file) with comments and blank space removed (a change of
     comments does not change the kernels the counters measured)."""
     import glob
     import hashlib
@@ -236,6 +236,148 @@ def _worker_init_probe(_):
     return os.getpid()
 
 
+# ---------------------------------------------------------------------------- extra legs
+def _time_calls(torch, fn, steps, warmup=1):
+    """Mean seconds per call of fn() over `steps` calls (HIP events on the
+    current stream) after `warmup` untimed calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
+
+
+def leg_nside512(fl, torch, pool, nw):
+    """N_side 512, lmax 1024, K 24, T+Q+U: FP64 and FP32 + refinement, each
+    with its fallback fraction and a sampled parity check against the oracle."""
+    from workload import configs, spectra
+    sh = SHAPES["nside512"]
+    nside, lmax, K = sh["nside"], sh["lmax"], sh["K"]
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    m = configs.maps(2, nside, lmax, "TQU", "cuda")
+    th, ph = configs.lensing_targets(2, nside, lmax, "cuda")
+    inp = dict(T=m["T"], QU=torch.cat([m["Q"], m["U"]]), theta=th, phi=ph, tt=tt, ee=ee, bb=bb)
+    n = th.numel()
+    res = {"workload": f"lensing remap N_side {nside} lmax {lmax} K {K} T+Q+U, one displaced target per pixel"}
+    for prec, code in (("fp64", fl.FP64), ("fp32ir", fl.FP32_IR)):
+        p0 = fl.Plan(nside, lmax, tt, K, 0, precision=code)
+        p2 = fl.Plan(nside, lmax, np.concatenate([ee, bb]), K, 2, precision=code)
+        o = [torch.empty(k * n, dtype=torch.float64, device="cuda") for k in (1, 1, 2, 2)]
+        call = lambda: fl.interpolate_tqu(p0, p2, inp["T"], inp["QU"], th, ph, out_t=o[0], var_t=o[1],
+                                          out_qu=o[2], var_qu=o[3])
+        call()
+        torch.cuda.synchronize()
+        p0.reset_stats()
+        p2.reset_stats()
+        t = _time_calls(torch, call, steps=5, warmup=0)
+        st0, st2 = p0.stats(), p2.stats()
+        r = {"samples_per_s": 3.0 * n / t, "s_per_step": t, "tqu_shared": bool(fl.tqu_shared(p0, p2)),
+             "plan_precision_run": {"T": "fp64" if p0.info()["precision"] == fl.FP64 else "fp32ir",
+                                    "QU": "fp64" if p2.info()["precision"] == fl.FP64 else "fp32ir"},
+             "fp32_probe_reject": {"T": p0.info()["fp32_probe_reject"], "QU": p2.info()["fp32_probe_reject"]},
+             "fp64_recompute_fraction": {"T": st0["fp64_fallbacks"] / (5 * n),
+                                         "QU": st2["fp64_fallbacks"] / (5 * n)}}
+        if pool is not None:
+            _, par = cpu_baseline(pool, nw, sh, inp, o[0], o[1], o[2], o[3], 600, 2)
+            r["parity_sample"] = par
+        res[prec] = r
+    res["fp32ir_speedup_over_fp64"] = res["fp64"]["s_per_step"] / res["fp32ir"]["s_per_step"]
+    return res
+
+
+def leg_supersample(fl, torch):
+    """The paper's supersampling shape (Table 1): a T map at N_side 2048,
+    lmax 4096, interpolated at every pixel centre of N_side 4096, K = 9 and
+    36 nearest pixels.  Paper context: 3.3 min (K 9) and 19 min (K 36) on one
+    Xeon E5410 core with tabulated S^-1."""
+    from workload import configs, spectra
+    nside, nout, lmax = 2048, 4096, 4096
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    m = configs.maps(3, nside, lmax, "T", "cuda")["T"]
+    npo = 12 * nout * nout
+    out = torch.empty(npo, dtype=torch.float64, device="cuda")
+    var = torch.empty(npo, dtype=torch.float64, device="cuda")
+    res = {"workload": f"supersampling N_side {nside} -> {nout}, lmax {lmax}, T", "targets": npo}
+    paper_s = {9: 3.3 * 60, 36: 19 * 60}
+    for K in (9, 36):
+        p = fl.Plan(nside, lmax, tt, K, 0)
+        t = _time_calls(torch, lambda: fl.supersample(p, m, nout, out=out, var=var), steps=2)
+        res[f"K{K}"] = {"samples_per_s": npo / t, "s_per_map": t,
+                        "paper_cpu_s_per_map": paper_s[K],
+                        "paper_context": "Table 1, one Xeon E5410 2.33 GHz core, tabulated S^-1 stencil"}
+    return res
+
+
+def leg_serving(fl, torch, inp_main, rate=1.0, n_req=16):
+    """Serving: Poisson requests (rate per second) with N_side {256, 1024, 2048,
+    4096} (weights .4/.3/.2/.1), T or T+Q+U, K 32, lmax = N_side; each request
+    takes its maps and targets from a pre-generated pool (one seeded input set
+    per N_side; the N_side 4096 set is the main workload's), held in pinned host
+    memory and copied to the device at admission; admission by HBM footprint
+    over two streams."""
+    from paper_1003_4984_amd.serve import DeviceExecutor, PlanCache, Request, Server, report
+    from workload import configs, spectra
+    from workload.seeds import rng as seeded
+    nsides, weights = (256, 1024, 2048, 4096), np.array([0.4, 0.3, 0.2, 0.1])
+    pin = lambda x: x.cpu().pin_memory()
+    pool_in = {}
+    for ns in nsides:
+        if ns == 4096:
+            mt, mqu, th, ph = inp_main["T"], inp_main["QU"], inp_main["theta"], inp_main["phi"]
+        else:
+            m = configs.maps(5, ns, ns, "TQU", "cuda", job=ns)
+            mt, mqu = m["T"], torch.cat([m["Q"], m["U"]])
+            th, ph = configs.lensing_targets(5, ns, ns, "cuda", job=ns)
+        pool_in[ns] = {"T": pin(mt), "QU": pin(mqu), "theta": pin(th), "phi": pin(ph)}
+    torch.cuda.synchronize()
+    g = seeded(5, 0, 4)
+    t, reqs = 0.0, []
+    for i in range(n_req):
+        t += g.exponential(1.0 / rate)
+        ns = int(g.choice(nsides, p=weights / weights.sum()))
+        fields = "TQU" if g.uniform() < 0.5 else "T"
+        tt, ee, te, bb = spectra.cl_acoustic(ns)
+        src = pool_in[ns]
+        host = {"T": src["T"], "theta": src["theta"], "phi": src["phi"]}
+        if fields == "TQU":
+            host["QU"] = src["QU"]
+        reqs.append(Request(rid=i, arrival=t, nside=ns, lmax=ns, K=32, fields=fields, n=src["theta"].numel(),
+                            cl_tt=tt, cl_ee=ee, cl_bb=bb, host=host))
+    plans = PlanCache(lambda nside, lmax, cl, K, spin: fl.Plan(nside, lmax, cl, K, spin))
+    plans.warm(reqs)
+    ex = DeviceExecutor(plans, slots=2, tqu_shared=True)
+    srv = Server(ex, hbm_budget=160 * 2 ** 30, slots=2, plans=plans)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    rep = report(done, time.perf_counter() - t0)
+    rep.update({"rate_per_s": rate, "K": 32, "nsides": list(nsides), "weights": weights.tolist(),
+                "slots": 2, "hbm_budget_gib": 160, "peak_admitted_gib": srv.peak / 2 ** 30,
+                "inputs": "pinned host memory, copied to the device at admission"})
+    del pool_in
+    return rep
+
+
+def run_legs(fl, torch, inp_main, pool, nw):
+    legs = {}
+    for name, fn in (("nside512_fp64_vs_fp32ir", lambda: leg_nside512(fl, torch, pool, nw)),
+                     ("supersample_2048_to_4096", lambda: leg_supersample(fl, torch)),
+                     ("serving_cfg5", lambda: leg_serving(fl, torch, inp_main))):
+        log(f"leg {name}")
+        try:
+            legs[name] = fn()
+        except Exception as e:           # a failed leg is reported, the headline stands
+            legs[name] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return legs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +390,8 @@ def main():
     ap.add_argument("--tqu", default="shared", choices=["shared", "separate"],
                     help="T and Q/U in one call sharing the stencil search (shared), or one "
                          "call per plan (separate)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the extra measurements (N_side 512 FP64 and FP32+IR, supersampling, serving)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy of "
                          "known size that calibrates HBM traffic counters)")
@@ -286,6 +430,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     shared = args.tqu == "shared"
+    tqu_mode = args.tqu
+    if shared and not fl.tqu_shared(p0, p2):
+        tqu_mode = "shared call running as two searching calls (plans not shareable)"
 
     def step(ev=None):
         if ev:
@@ -328,7 +475,7 @@ def main():
         fpp = flops_spin0(K) + flops_spin2(K)
         achieved = fpp * n / t_spin0.mean() / 1e12
         kname = ("T+Q/U call with shared stencils (12 x k_interp_tile_st<4> + 12 x k_interp_rs_ld<2> "
-                 "+ two fix-up scans)")
+                 "+ two fix-up scans)") if tqu_mode == "shared" else "T+Q/U call (" + tqu_mode + ")"
         kernel_s = {"tqu": float(t_spin0.mean())}
         tunit = "HBM bytes per T+Q/U call (rocprofv3 FETCH_SIZE + WRITE_SIZE, all its kernels)"
     else:
@@ -352,8 +499,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"lensing remap N_side {shape['nside']} lmax {shape['lmax']} "
                                f"K {K} T+Q+U, one displaced target per pixel",
-                   "points": n, "precision": args.precision, "spin2_mode": "full", "tqu": args.tqu,
-                   "nugget": "always (eps = 2^-26)"},
+                   "points": n, "precision": args.precision, "spin2_mode": "full", "tqu": tqu_mode,
+                   "nugget": "always (eps = 2^-26)",
+                   "plan_precision_run": {"T": "fp64" if p0.info()["precision"] == fl.FP64 else "fp32ir",
+                                          "QU": "fp64" if p2.info()["precision"] == fl.FP64 else "fp32ir"},
+                   "fp32_probe_reject": {"T": p0.info()["fp32_probe_reject"],
+                                         "QU": p2.info()["fp32_probe_reject"]}},
         "points_per_s": n * args.steps / wall,
         "latency_s": {"p50": float(np.percentile(step_t, 50)), "p99": float(np.percentile(step_t, 99)),
                       "note": "per full-sky request (T, Q and U), HIP events"},
@@ -368,11 +519,15 @@ def main():
         log(f"oracle on {args.cpu_sample} sampled targets")
         base, parity = cpu_baseline(pool, nw, shape, inp, out_t, var_t, out_qu, var_qu, args.cpu_sample,
                                     shape["cfg"])
-        pool.close()
-        pool.join()
         result["cpu_baseline"] = base
         result["parity_sample"] = parity
         result["parity_ok"] = parity["parity_ok"]
+    if not args.no_legs and args.workload == "nside4096":
+        out_t = var_t = out_qu = var_qu = None      # the legs need the memory
+        result["legs"] = run_legs(fl, torch, inp, pool, nw)
+    if pool is not None:
+        pool.close()
+        pool.join()
     print(json.dumps(result), flush=True)
     if result.get("parity_ok") is False:
         log("parity sample outside the tolerance: " + json.dumps(result["parity_sample"]))

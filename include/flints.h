@@ -55,6 +55,7 @@ enum { FLINTS_FP64 = 0, FLINTS_FP32_IR = 1 };
 enum { FLINTS_S2_FULL = 0, FLINTS_S2_PAPER = 1 };
 enum { FLINTS_NUG_ALWAYS = 0, FLINTS_NUG_ON_FAILURE = 1 };
 enum { FLINTS_VAR_PAPER = 0, FLINTS_VAR_MSE = 1 };
+enum { FLINTS_STENCIL_NEAREST = 0, FLINTS_STENCIL_PIXEL = 1 };
 
 typedef struct {
   /* FLINTS_FP64: every step in double precision.
@@ -83,6 +84,25 @@ typedef struct {
    * the FP32 factor, and maximum |dw| / |w| of the refinement step. */
   double pivot_ratio_min;
   double refine_tol;
+  /* FP32_IR plans probe their neighbour systems when created: the FP32
+   * factorisation and refinement run (with zero data) on 512 fixed directions
+   * spread over the sphere, and if more than this fraction of them is rejected
+   * the plan computes in FP64 from the start, since an FP32 attempt that is
+   * recomputed in FP64 only adds work (0 = default 0.5; >= 1 never skips).
+   * The fraction found is reported by flints_plan_info. */
+  double fp32_max_reject;
+  /* FLINTS_STENCIL_NEAREST (default): the K pixel centres nearest to each
+   *   target, and a factorisation per target (O(K^3) per target).
+   * FLINTS_STENCIL_PIXEL: the paper's stencil tied to the pixel containing the
+   *   target (Sec. 2.3), read as the K pixel centres nearest to that pixel's
+   *   centre, with the Cholesky factor of every pixel class tabulated at plan
+   *   time (Sec. 2.4, one factor per ring position using the quarter-turn and
+   *   belt rotations of the pixelisation), so a target costs two triangular
+   *   solves (O(K^2)).  Needs at most 48 rows (spin 0: K <= 48; spin 2:
+   *   K <= 16), FLINTS_VAR_PAPER, and computes in FP64; the tables take
+   *   about N_side^2 classes x (4 K + 4 n (n + 1)) bytes (n = K or 2K) of
+   *   device memory, reported by flints_plan_info. */
+  int stencil;
 } flints_opts;
 
 /* Fill *o with the defaults above. */
@@ -97,8 +117,10 @@ void flints_default_opts(flints_opts *o);
  *          correlation_func sums from l = 1).  spin 2: C^EE_l for l = 0..lmax
  *          followed by C^BB_l for l = 0..lmax (l < 2 ignored).  Must be finite
  *          and non-negative; read during the call only.
- *   K      stencil size, 1 <= K <= min(64, 12 nside^2) for spin 0 and
- *          1 <= K <= 32 for spin 2.
+ *   K      stencil size, 1 <= K <= min(64, 12 nside^2).  Spin 2 solves a 2K x 2K
+ *          system: up to 64 rows every option applies; above (K > 32) the plan
+ *          runs FP64 (an FLINTS_FP32_IR request computes in FP64, reported by
+ *          flints_plan_info) and FLINTS_VAR_MSE is refused.
  *   spin   0 (temperature) or 2 (Q, U polarisation).
  * The correlation function is built on the current HIP device in FP64 and kept
  * in device memory.  Returns NULL on error (see flints_last_error()).
@@ -144,7 +166,9 @@ int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
  * flints_tqu_shared); other plan pairs, or a failed allocation of the stencil
  * buffer, run as the two separate calls on the same stream.  The buffer holds
  * K ints per target for chunks of up to 2^24 targets (2 GiB at K = 32) and is
- * allocated and freed on the stream (hipMallocAsync / hipFreeAsync).  Invalid
+ * allocated and freed on the stream from a memory pool of the library that
+ * keeps freed memory (hipMallocFromPoolAsync / hipFreeAsync), so repeated
+ * calls reuse it.  Invalid
  * targets and failed searches are counted in both plans.  Returns
  * FLINTS_EINVAL for NULL plans or pointers, spins other than (0, 2), or
  * differing nside or K; n = 0 is a no-op.
@@ -152,6 +176,25 @@ int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
 int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
                            const void *map_qu, const double *theta, const double *phi, int64_t n,
                            void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream);
+
+/*
+ * Supersampling (paper Sec. 2.6, Table 1: a map of resolution N_side
+ * interpolated onto the pixel centres of resolution 2 N_side): interpolate the
+ * plan's RING map at every pixel centre of a RING map of resolution nside_out.
+ * The target directions are generated on the device (RING order of nside_out,
+ * pixel centres as in flints_plan's geometry), then the call is
+ * flints_interpolate over them.
+ *   map        as flints_interpolate (the plan's N_side).
+ *   nside_out  1 <= nside_out <= 16384; npix_out = 12 nside_out^2 targets.
+ *   out        device double[npix_out] (spin 2: [2][npix_out], the Q map then
+ *              the U map), a RING map of nside_out.
+ *   var        device, nullable, same layout.
+ * A workspace of 16 B per output pixel (the directions) is taken from the
+ * library's stream-ordered pool for the duration of the call.  Returns
+ * FLINTS_ENOMEM if it cannot be allocated.
+ */
+int flints_supersample(flints_plan_t plan, const void *map, int64_t nside_out, void *out, void *var,
+                       void *stream);
 
 /* 1 if flints_interpolate_tqu shares the stencil search between these plans
  * (with_var_*: whether variances will be requested), 0 if it runs two
@@ -185,6 +228,14 @@ typedef struct {
   double sigma2;         /* prior variance per output field */
   double search_r0, search_rcap;   /* stencil search radii (rad) */
   double nugget_eps;
+  int precision;         /* arithmetic the plan runs: FLINTS_FP64, or FLINTS_FP32_IR if
+                            the FP32 path was kept after the creation probe */
+  double fp32_probe_reject;        /* FP32_IR plans: fraction of probe systems the
+                                      FP32 path rejected (-1 for FP64 plans) */
+  int stencil;                     /* FLINTS_STENCIL_NEAREST or FLINTS_STENCIL_PIXEL */
+  int64_t pixel_classes;           /* FLINTS_STENCIL_PIXEL: tabulated classes */
+  int64_t class_nuggets;           /* classes whose factor needed -lambda_min + eps */
+  int64_t table_bytes;             /* device bytes of the plan's tables */
 } flints_plan_info_t;
 
 int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info);
@@ -198,9 +249,13 @@ typedef struct {
   int64_t table_range;         /* pair distances beyond the table (clamped) */
 } flints_stats;
 
-/* Counters accumulated since plan creation (synchronises the device). */
-int flints_plan_stats(flints_plan_t plan, flints_stats *st);
-int flints_plan_reset_stats(flints_plan_t plan);
+/* Counters accumulated since plan creation or the last reset: read on `stream`
+ * (so they include all work enqueued on it before the call; work on other
+ * streams counts once it has completed), and the call waits for `stream` only.
+ * flints_plan_reset_stats enqueues the zeroing on `stream` (not for use inside a
+ * captured graph). */
+int flints_plan_stats(flints_plan_t plan, flints_stats *st, void *stream);
+int flints_plan_reset_stats(flints_plan_t plan, void *stream);
 
 /* Release a plan.  The caller must ensure no work using it is in flight. */
 void flints_plan_destroy(flints_plan_t plan);
@@ -214,7 +269,8 @@ void flints_plan_destroy(flints_plan_t plan);
  * correlation table into LDS when the job changes, and run the same per-point
  * arithmetic as flints_interpolate (results are bit-identical to it); spin 0
  * and spin 2 jobs mix freely within a class.  Jobs with FP32_IR or MSE-variance
- * plans run through the single-plan path in the same stream.  Batching is an
+ * plans, and jobs whose system has more than 64 rows (spin 2 with K > 32), run
+ * through the single-plan path in the same stream.  Batching is an
  * addition to the method: the paper interpolates one map at a time.
  */
 typedef struct {

@@ -68,6 +68,15 @@ def stencil(nside, theta, phi, K, rt=None, allvec=None):
         r *= 2.0
 
 
+def pixel_stencils(nside, theta, phi, K):
+    """Stencil tied to the pixel containing each direction (Sec. 2.3: the
+    neighbours of a direction are those of its pixel), read as the K pixel
+    centres nearest to the centre of that pixel (ties to the smaller index)."""
+    pix = healpix.ang2pix(nside, theta, phi)
+    thc, phc = healpix.pix2ang(nside, pix)
+    return stencils(nside, thc, phc, K)
+
+
 def stencils(nside, theta, phi, K):
     theta = np.atleast_1d(theta)
     phi = np.atleast_1d(phi)
@@ -256,7 +265,7 @@ def krige_spin2(t_theta, t_phi, nvec, et_n, ep_n, qvals, uvals, cl_ee, cl_bb,
 
 # --------------------------------------------------------------------------- driver
 def interpolate(nside, cl, K, spin, maps, theta, phi, mode="full", nugget="always",
-                var_kind="paper", stencil_idx=None, batch=256):
+                var_kind="paper", stencil_idx=None, batch=256, stencil_rule="nearest"):
     """Oracle interpolation of a RING map at directions (theta, phi).
 
     spin 0: cl = C^TT[0..lmax], maps = T[npix];  returns value (n,), var (n,).
@@ -264,6 +273,8 @@ def interpolate(nside, cl, K, spin, maps, theta, phi, mode="full", nugget="alway
     A map may also be given as a function pix -> values (for maps too large to
     hold on the host; only the stencil pixels are read).
     Directions with theta outside [0, pi] or non-finite give NaN.
+    stencil_rule "nearest": the K pixel centres nearest to each direction;
+    "pixel": the K nearest to the centre of the pixel containing it.
     Also returns the stencils (n, K) used.
     """
     theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
@@ -274,7 +285,8 @@ def interpolate(nside, cl, K, spin, maps, theta, phi, mode="full", nugget="alway
         stencil_idx = np.full((n, K), -1, dtype=np.int64)
         gi = np.nonzero(good)[0]
         if gi.size:
-            stencil_idx[gi] = stencils(nside, theta[gi], phi[gi], K)
+            rule = pixel_stencils if stencil_rule == "pixel" else stencils
+            stencil_idx[gi] = rule(nside, theta[gi], phi[gi], K)
     shape = (n,) if spin == 0 else (n, 2)
     val = np.full(shape, np.nan)
     var = np.full(shape, np.nan)

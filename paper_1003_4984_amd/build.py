@@ -10,11 +10,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflints.so")
-SOURCES = ["capi.hip", "tables.hip", "interp.hip", "batch.hip"]
-# Stand-alone machine-peak probe (FP64 FMA, FP64 MFMA, copy bandwidth) for the
-# roofline figures; not part of the library.
-PEAKS_SRC = "peaks.hip"
-PEAKS_BIN = os.path.join(HERE, "flints_peaks")
+# interp_*.hip each instantiate one spin / precision class of the kernels so
+# that the translation units compile in parallel.
+SOURCES = ["capi.hip", "tables.hip", "interp.hip", "interp_s0.hip", "interp_s2.hip", "interp_f32_s0.hip",
+           "interp_f32_s2.hip", "interp_mse64_s0.hip", "interp_mse64_s2.hip", "interp_mse32_s0.hip",
+           "interp_mse32_s2.hip", "interp_tqu.hip", "supersample.hip", "fixed.hip", "batch.hip"]
 ARCH = os.environ.get("FLINTS_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled: some of their forms have produced wrong
@@ -42,10 +42,6 @@ def build(verbose=False, jobs=None):
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         objs.append(obj)
-    pcmd = [cc, *HIP_FLAGS, os.path.join(CSRC, PEAKS_SRC), "-o", PEAKS_BIN]
-    if verbose:
-        print(" ".join(pcmd), flush=True)
-    procs.append((PEAKS_SRC, subprocess.Popen(pcmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:
         out, _ = p.communicate()

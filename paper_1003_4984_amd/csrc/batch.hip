@@ -144,7 +144,9 @@ struct Batch {
 // beside tables of at most 16, 36, 57, 77 and 98 KB.
 static int job_class(const Plan *p) {
   if (p->d.precision != FLINTS_FP64 || p->d.var_kind != FLINTS_VAR_PAPER) return -1;
+  if (p->d.stencil_mode != FLINTS_STENCIL_NEAREST) return -1;   // tabulated stencils: own kernel
   const int n = p->d.n;
+  if (n > 64) return -1;   // the multi-pass engine runs through the single-plan path
   const int e = n <= 16 ? 0 : n <= 32 ? 1 : n <= 48 ? 2 : 3;
   const int tb = p->d.ntab * p->d.nfun * 8;
   static const int edge_kb[NTABB - 1] = {16, 36, 57, 77, 98};
@@ -274,6 +276,18 @@ static int enqueue(Batch *b, hipStream_t s) {
   return FLINTS_OK;
 }
 
+// Host-to-device upload on a private non-blocking stream of default priority,
+// so that creating a batch does not wait for work in flight on other streams
+// (a plain hipMemcpy runs on the null stream).
+static bool upload(void *dst, const void *src, size_t bytes) {
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
+  const bool ok = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess &&
+                  hipStreamSynchronize(st) == hipSuccess;
+  (void)hipStreamDestroy(st);
+  return ok;
+}
+
 // Time one class's main pass over a sample of the batch for a candidate tile
 // size and waves-per-block cap; returns seconds (or a large value on failure).
 static double time_candidate(Batch *b, int c, int tile_pts, int wpb_cap, int64_t limit) {
@@ -391,7 +405,11 @@ flints_batch_t flints_batch_create(const flints_job_t *jobs, int njobs, int flag
     free_batch(b);
     return nullptr;
   }
-  hipMemcpy(b->d_jobs, hj.data(), sizeof(BatchJob) * njobs, hipMemcpyHostToDevice);
+  if (!upload(b->d_jobs, hj.data(), sizeof(BatchJob) * njobs)) {
+    set_error("upload of the batch job table failed");
+    free_batch(b);
+    return nullptr;
+  }
   for (int c = 0; c < NCLASS; ++c) {
     ClassRun &r = b->run[c];
     if (!r.used) continue;
@@ -404,7 +422,11 @@ flints_batch_t flints_batch_create(const flints_job_t *jobs, int njobs, int flag
       free_batch(b);
       return nullptr;
     }
-    hipMemcpy(r.d_tiles, t.data(), sizeof(BatchTile) * t.size(), hipMemcpyHostToDevice);
+    if (!t.empty() && !upload(r.d_tiles, t.data(), sizeof(BatchTile) * t.size())) {
+      set_error("upload of the tile list failed");
+      free_batch(b);
+      return nullptr;
+    }
   }
   if (hipGetLastError() != hipSuccess) {
     set_error("batch set-up failed on the device");

@@ -36,6 +36,8 @@ void flints_default_opts(flints_opts *o) {
   o->table_tol = 1e-12;
   o->pivot_ratio_min = 0.0;
   o->refine_tol = 0.0;
+  o->fp32_max_reject = 0.0;
+  o->stencil = FLINTS_STENCIL_NEAREST;
 }
 
 const char *flints_last_error(void) { return g_last_error.c_str(); }
@@ -59,15 +61,33 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
   }
   if (!cl) { set_error("cl is NULL"); return nullptr; }
   const int64_t npix = 12 * nside * nside;
-  const int kmax = spin == 0 ? 64 : 32;
-  if (K < 1 || K > kmax || K > npix) {
-    set_error(spin == 0 ? "K must be in [1, min(64, npix)]" : "K must be in [1, min(32, npix)] for spin 2");
+  if (K < 1 || K > 64 || K > npix) {
+    set_error("K must be in [1, min(64, npix)]");
     return nullptr;
   }
   if (o.precision != FLINTS_FP64 && o.precision != FLINTS_FP32_IR) { set_error("bad precision"); return nullptr; }
   if (o.spin2_mode != FLINTS_S2_FULL && o.spin2_mode != FLINTS_S2_PAPER) { set_error("bad spin2_mode"); return nullptr; }
   if (o.nugget != FLINTS_NUG_ALWAYS && o.nugget != FLINTS_NUG_ON_FAILURE) { set_error("bad nugget policy"); return nullptr; }
   if (o.var_kind != FLINTS_VAR_PAPER && o.var_kind != FLINTS_VAR_MSE) { set_error("bad var_kind"); return nullptr; }
+  if (o.stencil != FLINTS_STENCIL_NEAREST && o.stencil != FLINTS_STENCIL_PIXEL) { set_error("bad stencil"); return nullptr; }
+  if (o.stencil == FLINTS_STENCIL_PIXEL) {
+    if ((spin == 0 && K > 48) || (spin == 2 && K > 16)) {
+      set_error("FLINTS_STENCIL_PIXEL supports at most 48 rows (spin 0: K <= 48, spin 2: K <= 16)");
+      return nullptr;
+    }
+    if (o.var_kind != FLINTS_VAR_PAPER) {
+      set_error("FLINTS_STENCIL_PIXEL supports FLINTS_VAR_PAPER only");
+      return nullptr;
+    }
+    if (nside > 8191) {
+      set_error("FLINTS_STENCIL_PIXEL supports nside <= 8191");
+      return nullptr;
+    }
+  }
+  if (o.var_kind == FLINTS_VAR_MSE && spin == 2 && K > 32) {
+    set_error("FLINTS_VAR_MSE supports systems of up to 64 rows (spin 2: K <= 32)");
+    return nullptr;
+  }
   const int ncl = (spin == 0 ? 1 : 2) * (lmax + 1);
   if (!finite_nonneg(cl, ncl)) { set_error("cl must be finite and non-negative"); return nullptr; }
 
@@ -140,6 +160,26 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
     return nullptr;
   }
   d.counters = p->d_counters;
+  d.stencil_mode = o.stencil;
+  if (o.stencil == FLINTS_STENCIL_PIXEL) {
+    d.precision = FLINTS_FP64;           // the tabulated factors are FP64
+    if (build_fixed(p) != FLINTS_OK) {
+      flints_plan_destroy(reinterpret_cast<flints_plan_t>(p));
+      return nullptr;
+    }
+  }
+  if (d.precision == FLINTS_FP32_IR && d.n > 64) {
+    d.precision = FLINTS_FP64;   // the FP32 engines hold at most 64 rows
+  } else if (d.precision == FLINTS_FP32_IR) {
+    const double maxrej = o.fp32_max_reject > 0.0 ? o.fp32_max_reject : 0.5;
+    const double rej = fp32_probe(p);
+    if (rej < 0.0) {
+      flints_plan_destroy(reinterpret_cast<flints_plan_t>(p));
+      return nullptr;
+    }
+    p->fp32_reject = rej;
+    if (rej > maxrej) d.precision = FLINTS_FP64;   // FP32 would only add work here
+  }
   return reinterpret_cast<flints_plan_t>(p);
 }
 
@@ -157,10 +197,9 @@ int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
                             (hipStream_t)stream);
 }
 
-int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
-                           const void *map_qu, const double *theta, const double *phi, int64_t n,
-                           void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream) {
-  g_last_error.clear();
+static int check_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t, const void *map_qu,
+                     const double *theta, const double *phi, int64_t n, const void *out_t,
+                     const void *out_qu) {
   if (!plan_t || !plan_qu) { set_error("plans must be non-NULL"); return FLINTS_EINVAL; }
   const Plan *p0 = as_plan(plan_t), *p2 = as_plan(plan_qu);
   if (p0->d.spin != 0 || p2->d.spin != 2) {
@@ -172,14 +211,32 @@ int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const vo
     return FLINTS_EINVAL;
   }
   if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
-  if (n == 0) return FLINTS_OK;
-  if (!map_t || !map_qu || !theta || !phi || !out_t || !out_qu) {
+  if (n > 0 && (!map_t || !map_qu || !theta || !phi || !out_t || !out_qu)) {
     set_error("maps, theta, phi and outputs must be non-NULL");
     return FLINTS_EINVAL;
   }
-  return launch_interpolate_tqu(p0, p2, (const double *)map_t, (const double *)map_qu, theta, phi, n,
-                                (double *)out_t, (double *)var_t, (double *)out_qu, (double *)var_qu,
-                                (hipStream_t)stream);
+  return FLINTS_OK;
+}
+
+int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
+                           const void *map_qu, const double *theta, const double *phi, int64_t n,
+                           void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream) {
+  g_last_error.clear();
+  const int rc = check_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, n, out_t, out_qu);
+  if (rc != FLINTS_OK || n == 0) return rc;
+  return launch_interpolate_tqu(as_plan(plan_t), as_plan(plan_qu), (const double *)map_t,
+                                (const double *)map_qu, theta, phi, n, (double *)out_t, (double *)var_t,
+                                (double *)out_qu, (double *)var_qu, (hipStream_t)stream);
+}
+
+int flints_supersample(flints_plan_t plan, const void *map, int64_t nside_out, void *out, void *var,
+                       void *stream) {
+  g_last_error.clear();
+  if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
+  if (nside_out < 1 || nside_out > 16384) { set_error("nside_out must be in [1, 16384]"); return FLINTS_EINVAL; }
+  if (!map || !out) { set_error("map and out must be non-NULL"); return FLINTS_EINVAL; }
+  return launch_supersample(as_plan(plan), (const double *)map, nside_out, (double *)out, (double *)var,
+                            (hipStream_t)stream);
 }
 
 int flints_tqu_shared(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu) {
@@ -225,15 +282,25 @@ int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info) {
   info->search_r0 = p->d.r0;
   info->search_rcap = p->d.rcap;
   info->nugget_eps = p->d.eps;
+  info->precision = p->d.precision;
+  info->fp32_probe_reject = p->fp32_reject;
+  info->stencil = p->d.stencil_mode;
+  info->pixel_classes = p->nclass;
+  info->class_nuggets = p->class_nuggets;
+  info->table_bytes = (int64_t)p->d.ntab * p->d.nfun * 8 +
+                      (p->nclass ? p->nclass * ((int64_t)p->d.K * 4 + (int64_t)p->d.lsz * 8) +
+                                       (int64_t)(4 * p->d.nside) * 12
+                                 : 0);
   return FLINTS_OK;
 }
 
-int flints_plan_stats(flints_plan_t plan, flints_stats *st) {
+int flints_plan_stats(flints_plan_t plan, flints_stats *st, void *stream) {
   g_last_error.clear();
   if (!plan || !st) { set_error("plan and stats must be non-NULL"); return FLINTS_EINVAL; }
   unsigned long long c[CNT_N];
-  if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(c, as_plan(plan)->d_counters, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) {
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(c, as_plan(plan)->d_counters, sizeof(c), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
     set_error("reading plan counters failed");
     return FLINTS_EDEVICE;
   }
@@ -246,11 +313,11 @@ int flints_plan_stats(flints_plan_t plan, flints_stats *st) {
   return FLINTS_OK;
 }
 
-int flints_plan_reset_stats(flints_plan_t plan) {
+int flints_plan_reset_stats(flints_plan_t plan, void *stream) {
   g_last_error.clear();
   if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
-  if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemset(as_plan(plan)->d_counters, 0, sizeof(unsigned long long) * CNT_N) != hipSuccess) {
+  if (hipMemsetAsync(as_plan(plan)->d_counters, 0, sizeof(unsigned long long) * CNT_N,
+                     (hipStream_t)stream) != hipSuccess) {
     set_error("resetting plan counters failed");
     return FLINTS_EDEVICE;
   }
@@ -262,6 +329,7 @@ void flints_plan_destroy(flints_plan_t plan) {
   Plan *p = as_plan(plan);
   if (p->d_tab) hipFree(p->d_tab);
   if (p->d_counters) hipFree(p->d_counters);
+  free_fixed(p);
   delete p;
 }
 

@@ -1,0 +1,11 @@
+// Register-row launchers of the MSE variance, FP64, spin 0.
+#include "interp_kernels.h"
+
+namespace flints {
+
+int launch_mse_fp64_s0(const Plan *p, const double *map, const double *theta, const double *phi,
+                       int64_t n, double *out, double *var, hipStream_t s) {
+  return launch_spin<0, true, false>(p, map, theta, phi, n, out, var, s);
+}
+
+}  // namespace flints

@@ -31,6 +31,16 @@ struct PlanDev {
   double pivot_ratio_min, refine_tol;
   const double *tab;   // [ntab][nfun], normalised correlation values
   unsigned long long *counters;  // [CNT_N]
+  // Stencil tied to the containing pixel (FLINTS_STENCIL_PIXEL): per ring its
+  // first class and quadrant size (0: one class for the whole ring), per class
+  // the stencil of its representative pixel as (ring << 16 | j) and the
+  // Cholesky factor of S + n I (packed rows, 1 / L_ii on the diagonal).
+  int32_t stencil_mode;
+  int32_t lsz;         // doubles per class factor, n (n + 1) / 2
+  const int64_t *cls_base;   // [4 nside] (index by ring)
+  const int32_t *cls_quad;   // [4 nside]
+  const int32_t *cls_stn;    // [nclass][K]
+  const double *cls_L;       // [nclass][lsz]
 };
 
 struct Plan {
@@ -38,6 +48,13 @@ struct Plan {
   int device;
   int lmax;
   double table_err;
+  int64_t nclass = 0;          // pixel classes of the fixed-stencil tables
+  int64_t class_nuggets = 0;   // classes whose factorisation needed -lambda_min + eps
+  int64_t *d_cls_base = nullptr;
+  int32_t *d_cls_quad = nullptr;
+  int32_t *d_cls_stn = nullptr;
+  double *d_cls_L = nullptr;
+  double fp32_reject = -1.0;   // FP32 probe: fraction of systems rejected (-1: not probed)
   double *d_tab = nullptr;
   unsigned long long *d_counters = nullptr;
 };
@@ -58,5 +75,22 @@ bool tqu_shareable(const Plan *p0, const Plan *p2, const double *var0, const dou
 int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_t n,
                    int64_t *idx, hipStream_t s);
 int launch_table_eval(const Plan *p, const double *s, int64_t n, double *out, hipStream_t st);
+// Stream-ordered workspace pool of the current device (interp_tqu.hip);
+// nullptr if pools are unsupported.
+hipMemPool_t workspace_pool();
+// Supersampling (supersample.hip): every pixel centre of a RING map of nside_out.
+int launch_supersample(const Plan *p, const double *map, int64_t nside_out, double *out, double *var,
+                       hipStream_t s);
+// Fixed-stencil tables (fixed.hip): classes, representative stencils and
+// factors; and the per-target and stencil launchers of that mode.
+int build_fixed(Plan *p);
+void free_fixed(Plan *p);
+int launch_fixed(const Plan *p, const double *map, const double *theta, const double *phi, int64_t n,
+                 double *out, double *var, hipStream_t s);
+int launch_fixed_stencil(const Plan *p, const double *theta, const double *phi, int64_t n, int64_t *idx,
+                         hipStream_t s);
+// FP32_IR conditioning probe (interp.hip): fraction of fixed probe systems the
+// FP32 path rejects, in [0, 1], or < 0 with the error set.
+double fp32_probe(Plan *p);
 
 }  // namespace flints

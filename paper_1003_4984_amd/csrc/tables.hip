@@ -94,6 +94,25 @@ int launch_table_eval(const Plan *p, const double *s, int64_t n, double *out, hi
   return FLINTS_OK;
 }
 
+// Device buffer owned for the duration of the table build; freed on every
+// return path unless released to the plan.
+struct DevBuf {
+  double *p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { reset(); }
+  void reset(double *q = nullptr) {
+    if (p) (void)hipFree(p);
+    p = q;
+  }
+  double *release() {
+    double *q = p;
+    p = nullptr;
+    return q;
+  }
+};
+
 #define HIPCHK(x)                                                   \
   do {                                                              \
     hipError_t e_ = (x);                                            \
@@ -113,43 +132,40 @@ int build_table(Plan *p, const double *w_plus, const double *w_minus, double tol
   for (int l = 0; l <= lmax; ++l) norm += w_plus[l];
   const double inv_norm = 1.0 / norm;
 
-  double *d_wp = nullptr, *d_wm = nullptr, *d_tmp = nullptr, *d_s = nullptr, *d_int = nullptr;
-  HIPCHK(hipMalloc(&d_wp, sizeof(double) * (lmax + 1)));
-  HIPCHK(hipMalloc(&d_wm, sizeof(double) * (lmax + 1)));
-  HIPCHK(hipMemcpy(d_wp, w_plus, sizeof(double) * (lmax + 1), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(d_wm, w_minus ? w_minus : w_plus, sizeof(double) * (lmax + 1),
+  DevBuf d_wp, d_wm, best_tab;
+  HIPCHK(hipMalloc(&d_wp.p, sizeof(double) * (lmax + 1)));
+  HIPCHK(hipMalloc(&d_wm.p, sizeof(double) * (lmax + 1)));
+  HIPCHK(hipMemcpy(d_wp.p, w_plus, sizeof(double) * (lmax + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_wm.p, w_minus ? w_minus : w_plus, sizeof(double) * (lmax + 1),
                    hipMemcpyHostToDevice));
 
   int nint = 128;                 // intervals over [0, smax]
   double best_err = 1e300;
-  double *best_tab = nullptr;
   int best_ntab = 0;
   double best_h = 0.0;
   for (int iter = 0; iter < 12; ++iter) {
     const int ntab = nint + 4;
     const double h = p->d.smax / (double)nint;
-    double *d_tab = nullptr;
-    HIPCHK(hipMalloc(&d_tab, sizeof(double) * ntab * nf));
+    DevBuf d_tab, d_tmp, d_s, d_int;
+    HIPCHK(hipMalloc(&d_tab.p, sizeof(double) * ntab * nf));
     int th = 128;
-    hipLaunchKernelGGL(k_table_nodes, dim3((ntab + th - 1) / th), dim3(th), 0, 0, d_wp, d_wm,
-                       lmax, spin, inv_norm, h, -1.0, ntab, d_tab);
+    hipLaunchKernelGGL(k_table_nodes, dim3((ntab + th - 1) / th), dim3(th), 0, 0, d_wp.p, d_wm.p,
+                       lmax, spin, inv_norm, h, -1.0, ntab, d_tab.p);
     // exact values at interval midpoints s = (m + 1/2) h, m = 0 .. nint-1
-    HIPCHK(hipMalloc(&d_tmp, sizeof(double) * nint * nf));
-    hipLaunchKernelGGL(k_table_nodes, dim3((nint + th - 1) / th), dim3(th), 0, 0, d_wp, d_wm,
-                       lmax, spin, inv_norm, h, 0.5, nint, d_tmp);
+    HIPCHK(hipMalloc(&d_tmp.p, sizeof(double) * nint * nf));
+    hipLaunchKernelGGL(k_table_nodes, dim3((nint + th - 1) / th), dim3(th), 0, 0, d_wp.p, d_wm.p,
+                       lmax, spin, inv_norm, h, 0.5, nint, d_tmp.p);
     std::vector<double> hs(nint);
     for (int m = 0; m < nint; ++m) hs[m] = (m + 0.5) * h;
-    HIPCHK(hipMalloc(&d_s, sizeof(double) * nint));
-    HIPCHK(hipMalloc(&d_int, sizeof(double) * nint * nf));
-    HIPCHK(hipMemcpy(d_s, hs.data(), sizeof(double) * nint, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_table_eval, dim3((nint + th - 1) / th), dim3(th), 0, 0, d_tab, ntab,
-                       nf, 1.0 / h, d_s, (int64_t)nint, d_int, (unsigned long long *)nullptr);
+    HIPCHK(hipMalloc(&d_s.p, sizeof(double) * nint));
+    HIPCHK(hipMalloc(&d_int.p, sizeof(double) * nint * nf));
+    HIPCHK(hipMemcpy(d_s.p, hs.data(), sizeof(double) * nint, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_table_eval, dim3((nint + th - 1) / th), dim3(th), 0, 0, d_tab.p, ntab,
+                       nf, 1.0 / h, d_s.p, (int64_t)nint, d_int.p, (unsigned long long *)nullptr);
     HIPCHK(hipGetLastError());
     std::vector<double> ex(nint * nf), ip(nint * nf);
-    HIPCHK(hipMemcpy(ex.data(), d_tmp, sizeof(double) * nint * nf, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(ip.data(), d_int, sizeof(double) * nint * nf, hipMemcpyDeviceToHost));
-    hipFree(d_tmp); hipFree(d_s); hipFree(d_int);
-    d_tmp = d_s = d_int = nullptr;
+    HIPCHK(hipMemcpy(ex.data(), d_tmp.p, sizeof(double) * nint * nf, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ip.data(), d_int.p, sizeof(double) * nint * nf, hipMemcpyDeviceToHost));
     double err = 0.0;
     bool finite = true;
     for (int i = 0; i < nint * nf; ++i) {
@@ -158,27 +174,21 @@ int build_table(Plan *p, const double *w_plus, const double *w_minus, double tol
       err = std::max(err, e);
     }
     if (!finite) {
-      hipFree(d_tab);
-      hipFree(d_wp); hipFree(d_wm);
-      if (best_tab) hipFree(best_tab);
       set_error("correlation table is not finite (check the spectrum)");
       return FLINTS_EINVAL;
     }
     const bool improved = err < 0.5 * best_err;
     if (err < best_err) {
-      if (best_tab) hipFree(best_tab);
-      best_tab = d_tab; best_err = err; best_ntab = ntab; best_h = h;
-    } else {
-      hipFree(d_tab);
+      best_tab.reset(d_tab.release());
+      best_err = err; best_ntab = ntab; best_h = h;
     }
     if (best_err <= tol || !improved || ntab >= NTAB_MAX) break;
     double grow = std::pow(best_err / tol, 0.25) * 1.15;
     grow = std::min(std::max(grow, 1.25), 8.0);
     nint = std::min(NTAB_MAX - 4, (int)std::ceil(nint * grow));
   }
-  hipFree(d_wp); hipFree(d_wm);
-  p->d_tab = best_tab;
-  p->d.tab = best_tab;
+  p->d_tab = best_tab.release();
+  p->d.tab = p->d_tab;
   p->d.ntab = best_ntab;
   p->d.nfun = nf;
   p->d.h = best_h;

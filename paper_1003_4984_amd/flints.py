@@ -16,6 +16,7 @@ FP64, FP32_IR = 0, 1
 S2_FULL, S2_PAPER = 0, 1
 NUG_ALWAYS, NUG_ON_FAILURE = 0, 1
 VAR_PAPER, VAR_MSE = 0, 1
+STENCIL_NEAREST, STENCIL_PIXEL = 0, 1
 
 _lib = None
 
@@ -28,7 +29,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("spin2_mode", ctypes.c_int),
                 ("nugget", ctypes.c_int), ("var_kind", ctypes.c_int),
                 ("table_tol", ctypes.c_double), ("pivot_ratio_min", ctypes.c_double),
-                ("refine_tol", ctypes.c_double)]
+                ("refine_tol", ctypes.c_double), ("fp32_max_reject", ctypes.c_double),
+                ("stencil", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -36,7 +38,10 @@ class _Info(ctypes.Structure):
                 ("spin", ctypes.c_int), ("ntab", ctypes.c_int), ("table_step", ctypes.c_double),
                 ("table_smax", ctypes.c_double), ("table_err", ctypes.c_double),
                 ("sigma2", ctypes.c_double), ("search_r0", ctypes.c_double),
-                ("search_rcap", ctypes.c_double), ("nugget_eps", ctypes.c_double)]
+                ("search_rcap", ctypes.c_double), ("nugget_eps", ctypes.c_double),
+                ("precision", ctypes.c_int), ("fp32_probe_reject", ctypes.c_double),
+                ("stencil", ctypes.c_int), ("pixel_classes", ctypes.c_int64),
+                ("class_nuggets", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
 
 
 class _Stats(ctypes.Structure):
@@ -61,6 +66,7 @@ BATCH_AUTOTUNE = 1
 
 EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
            "flints_interpolate_tqu", "flints_tqu_shared",
+           "flints_supersample",
            "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
            "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error",
            "flints_batch_create", "flints_batch_run", "flints_batch_capture", "flints_batch_info",
@@ -87,6 +93,8 @@ def load_library(path=LIB_PATH):
     lib.flints_interpolate.restype = c_int
     lib.flints_interpolate_tqu.argtypes = [vp, vp, dp, dp, dp, dp, i64, dp, dp, dp, dp, vp]
     lib.flints_interpolate_tqu.restype = c_int
+    lib.flints_supersample.argtypes = [vp, dp, i64, dp, dp, vp]
+    lib.flints_supersample.restype = c_int
     lib.flints_tqu_shared.argtypes = [vp, vp, c_int, c_int]
     lib.flints_tqu_shared.restype = c_int
     lib.flints_stencil.argtypes = [vp, dp, dp, i64, dp, vp]
@@ -95,9 +103,9 @@ def load_library(path=LIB_PATH):
     lib.flints_table_eval.restype = c_int
     lib.flints_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.flints_plan_info.restype = c_int
-    lib.flints_plan_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+    lib.flints_plan_stats.argtypes = [vp, ctypes.POINTER(_Stats), vp]
     lib.flints_plan_stats.restype = c_int
-    lib.flints_plan_reset_stats.argtypes = [vp]
+    lib.flints_plan_reset_stats.argtypes = [vp, vp]
     lib.flints_plan_reset_stats.restype = c_int
     lib.flints_plan_destroy.argtypes = [vp]
     lib.flints_plan_destroy.restype = None
@@ -151,7 +159,7 @@ class Plan:
 
     def __init__(self, nside, lmax, cl, K, spin, precision=FP64, spin2_mode=S2_FULL,
                  nugget=NUG_ALWAYS, var_kind=VAR_PAPER, table_tol=0.0,
-                 pivot_ratio_min=0.0, refine_tol=0.0):
+                 pivot_ratio_min=0.0, refine_tol=0.0, fp32_max_reject=0.0, stencil=STENCIL_NEAREST):
         lib = load_library()
         cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64).ravel())
         need = (lmax + 1) * (1 if spin == 0 else 2)
@@ -161,6 +169,8 @@ class Plan:
         lib.flints_default_opts(ctypes.byref(o))
         o.precision, o.spin2_mode, o.nugget, o.var_kind = precision, spin2_mode, nugget, var_kind
         o.table_tol, o.pivot_ratio_min, o.refine_tol = table_tol, pivot_ratio_min, refine_tol
+        o.fp32_max_reject = fp32_max_reject
+        o.stencil = stencil
         h = lib.flints_plan_ex(int(nside), int(lmax), cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                int(K), int(spin), ctypes.byref(o))
         if not h:
@@ -179,13 +189,16 @@ class Plan:
         _check(self._lib, self._lib.flints_plan_info(self._h, ctypes.byref(i)), "flints_plan_info")
         return {k: getattr(i, k) for k, _ in _Info._fields_}
 
-    def stats(self):
+    def stats(self, stream=None):
+        """Counters, read on `stream` (default: torch's current stream)."""
         s = _Stats()
-        _check(self._lib, self._lib.flints_plan_stats(self._h, ctypes.byref(s)), "flints_plan_stats")
+        _check(self._lib, self._lib.flints_plan_stats(self._h, ctypes.byref(s), _stream(stream)),
+               "flints_plan_stats")
         return {k: getattr(s, k) for k, _ in _Stats._fields_}
 
-    def reset_stats(self):
-        _check(self._lib, self._lib.flints_plan_reset_stats(self._h), "flints_plan_reset_stats")
+    def reset_stats(self, stream=None):
+        _check(self._lib, self._lib.flints_plan_reset_stats(self._h, _stream(stream)),
+               "flints_plan_reset_stats")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -247,15 +260,36 @@ def interpolate_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, out_t=None, var_
             or (var_qu is not None and var_qu.numel() != 2 * n)):
         raise FlintsError("outputs have the wrong size")
     lib = plan_t._lib
-    rc = lib.flints_interpolate_tqu(plan_t.handle, plan_qu.handle, _ptr(map_t, "map_t", torch.float64),
-                                    _ptr(map_qu, "map_qu", torch.float64),
-                                    _ptr(theta, "theta", torch.float64), _ptr(phi, "phi", torch.float64),
-                                    int(n), _ptr(out_t, "out_t", torch.float64),
-                                    _ptr(var_t, "var_t", torch.float64),
-                                    _ptr(out_qu, "out_qu", torch.float64),
-                                    _ptr(var_qu, "var_qu", torch.float64), _stream(stream))
+    fn = lib.flints_interpolate_tqu
+    rc = fn(plan_t.handle, plan_qu.handle, _ptr(map_t, "map_t", torch.float64),
+            _ptr(map_qu, "map_qu", torch.float64), _ptr(theta, "theta", torch.float64),
+            _ptr(phi, "phi", torch.float64), int(n), _ptr(out_t, "out_t", torch.float64),
+            _ptr(var_t, "var_t", torch.float64), _ptr(out_qu, "out_qu", torch.float64),
+            _ptr(var_qu, "var_qu", torch.float64), _stream(stream))
     _check(lib, rc, "flints_interpolate_tqu")
     return out_t, var_t, out_qu, var_qu
+
+
+def supersample(plan, map_, nside_out, out=None, var=None, want_var=True, stream=None):
+    """Interpolate `map_` (the plan's N_side) at every pixel centre of a RING
+    map of `nside_out` (flints_supersample).  Returns (out, var), RING maps of
+    nside_out (spin 2: the Q map then the U map)."""
+    import torch
+    if map_.numel() != plan.npix * plan.nfield:
+        raise FlintsError(f"map must hold {plan.npix * plan.nfield} values")
+    n = 12 * int(nside_out) * int(nside_out)
+    if out is None:
+        out = torch.empty(plan.nfield * n, dtype=torch.float64, device=map_.device)
+    if var is None and want_var:
+        var = torch.empty(plan.nfield * n, dtype=torch.float64, device=map_.device)
+    if out.numel() != plan.nfield * n or (var is not None and var.numel() != plan.nfield * n):
+        raise FlintsError("out/var have the wrong size")
+    lib = plan._lib
+    rc = lib.flints_supersample(plan.handle, _ptr(map_, "map", torch.float64), int(nside_out),
+                                _ptr(out, "out", torch.float64), _ptr(var, "var", torch.float64),
+                                _stream(stream))
+    _check(lib, rc, "flints_supersample")
+    return out, var
 
 
 def tqu_shared(plan_t, plan_qu, with_var=True):

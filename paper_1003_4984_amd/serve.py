@@ -1,17 +1,22 @@
 """Serving loop: continuous batching of lensing interpolation requests.
 
 Requests (a map set -- T, or T with Q/U -- plus displaced target directions)
-arrive over time.  The server keeps plans, and with them the device-resident
-correlation tables, in a cache keyed by (N_side, lmax, K, spin, spectrum); admits
-waiting requests first-come first-served while the HBM they need (outputs,
-variances, maps, targets and any new plan's table) fits a budget and a launch slot is free;
-groups the requests admitted at one step into one batched launch
-(flints_batch_*) on the next free stream, so work of different requests
-overlaps on the device -- except that a T+Q+U request runs through
+arrive over time with their inputs in host memory.  The server keeps plans, and
+with them the device-resident correlation tables, in a cache keyed by (N_side,
+lmax, K, spin, spectrum) that is filled before serving starts (the tables of
+the served configurations are built once, like the paper's initialisation
+step); admits waiting requests first-come first-served while the HBM they need
+(maps, targets, outputs, variances, the stencil buffer of a T+Q+U call and any
+new plan's table) fits a budget and a launch slot is free; copies the admitted
+requests' inputs to the device on the slot's stream and groups them into one
+batched launch (flints_batch_*) on that stream, so the work of different
+requests overlaps on the device -- except that a T+Q+U request runs through
 flints_interpolate_tqu on that stream (one K-nearest search per target serves
-both its plans); and releases a request's memory when its completion event
-has fired.  Latency is completion minus arrival; the report gives p50
-and p99 next to throughput in samples per second.
+both its plans); and releases a request's device memory when its completion
+event has fired.  Batch descriptors are destroyed only while no launch is in
+flight (freeing device memory waits for the whole device).  Latency is
+completion minus arrival; the report gives p50 and p99 next to throughput in
+samples per second.
 
 The scheduling logic is independent of the device: `Server` drives an
 executor with `launch(requests, slot) -> token` and `done(token) -> bool`;
@@ -29,6 +34,8 @@ import numpy as np
 
 BYTES_PER_SAMPLE = 16          # one double of output and one of variance
 TABLE_BYTES_BOUND = 256 * 1024  # plan table upper bound used for admission
+TQU_CHUNK = 1 << 24            # targets per stencil-buffer chunk of flints_interpolate_tqu
+BATCH_BYTES_BOUND = 1 << 20     # device job table, tile lists and queue counters of one batch
 
 
 @dataclass
@@ -43,9 +50,10 @@ class Request:
     cl_tt: object = None
     cl_ee: object = None
     cl_bb: object = None
-    maps: dict = field(default_factory=dict)   # "T": tensor, "QU": tensor (device)
+    maps: dict = field(default_factory=dict)   # "T": tensor, "QU": tensor (device, from admission)
     theta: object = None
     phi: object = None
+    host: dict = field(default_factory=dict)   # inputs in host memory: "T", "QU", "theta", "phi"
     out: dict = field(default_factory=dict)    # filled at admission: field set -> (out, var)
     admitted: float = None
     finished: float = None
@@ -54,13 +62,16 @@ class Request:
     def samples(self):
         return self.n * len(self.fields)
 
-    def footprint(self, new_tables=0):
+    def footprint(self, new_tables=0, tqu_shared=True):
         """HBM a request holds while admitted: its maps (f fields of 12 N_side^2
         doubles), its target directions (16 B each), outputs and variances
-        (16 B per sample) and the tables of plans not yet cached."""
+        (16 B per sample), the stencil buffer of a T+Q+U call (K int32 per
+        target of one 2^24-target chunk), a batch descriptor, and the tables of
+        plans not yet cached."""
         f = len(self.fields)
+        stencils = 4 * self.K * min(self.n, TQU_CHUNK) if (self.fields == "TQU" and tqu_shared) else 0
         return (8 * 12 * self.nside * self.nside * f + 16 * self.n + self.samples * BYTES_PER_SAMPLE
-                + new_tables * TABLE_BYTES_BOUND)
+                + stencils + BATCH_BYTES_BOUND + new_tables * TABLE_BYTES_BOUND)
 
 
 class PlanCache:
@@ -87,6 +98,13 @@ class PlanCache:
             self._plans[k] = self._make(nside, lmax, cl, K, spin)
         return self._plans[k]
 
+    def warm(self, requests):
+        """Build the plans (tables) every request needs, before serving."""
+        for r in requests:
+            self.get(r.nside, r.lmax, r.K, 0, r.cl_tt)
+            if r.fields == "TQU":
+                self.get(r.nside, r.lmax, r.K, 2, np.concatenate([r.cl_ee, r.cl_bb]))
+
     def __len__(self):
         return len(self._plans)
 
@@ -95,8 +113,10 @@ class Server:
     """Admission by HBM footprint, FIFO, continuous batching over `slots` streams."""
 
     def __init__(self, executor, hbm_budget, slots=2, plans=None, clock=time.perf_counter,
-                 max_group_samples=1 << 26):
+                 max_group_samples=1 << 26, sleep=time.sleep, tqu_shared=True):
         self.ex = executor
+        self.sleep = sleep
+        self.tqu_shared = tqu_shared
         self.budget = int(hbm_budget)
         self.max_group = int(max_group_samples)   # caps one launch so groups finish in turn
         self.slots = int(slots)
@@ -116,8 +136,10 @@ class Server:
         done = []
         while pending or waiting or running:
             now = self.clock() - t0
+            progress = False
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
+                progress = True
             # completions
             for slot in list(running):
                 token, reqs, nbytes = running[slot]
@@ -129,6 +151,9 @@ class Server:
                     self.in_use -= nbytes
                     del running[slot]
                     free.append(slot)
+                    progress = True
+            if not running and hasattr(self.ex, "quiesce"):
+                self.ex.quiesce()              # nothing in flight: release retired launches
             # admission: first come first served while memory and a slot allow
             if free and waiting:
                 group, nbytes, nsamp = [], 0, 0
@@ -136,7 +161,8 @@ class Server:
                     r = waiting[0]
                     if group and nsamp + r.samples > self.max_group:
                         break
-                    need = r.footprint(self.plans.missing(r) if self.plans is not None else 0)
+                    need = r.footprint(self.plans.missing(r) if self.plans is not None else 0,
+                                       self.tqu_shared)
                     if need > self.budget:
                         raise ValueError(f"request {r.rid} needs {need} B, more than the budget")
                     if self.in_use + nbytes + need > self.budget:
@@ -156,6 +182,11 @@ class Server:
                     continue
             if idle is not None:
                 idle()
+            elif not progress:
+                # nothing to do until the next arrival or a completion: yield
+                # the host thread instead of spinning
+                wait = pending[0].arrival - (self.clock() - t0) if pending else 1e-3
+                self.sleep(min(max(wait, 0.0), 2e-4 if running else 1e-3))
         return done
 
 
@@ -170,17 +201,24 @@ def report(done, wall):
 
 class DeviceExecutor:
     """FLINTS executor: one flints batch per admitted group, on `slots` streams
-    of default priority; completion via a recorded event.  With `tqu_shared`,
+    of default priority; the group's inputs are copied from host memory on the
+    slot's stream first; completion via a recorded event.  With `tqu_shared`,
     T+Q+U requests run through interpolate_tqu (shared stencil search) on the
-    group's stream instead of as two batch jobs."""
+    group's stream instead of as two batch jobs.  `keep_inputs` keeps the
+    requests' device inputs after completion (for checking results)."""
 
-    def __init__(self, plans, slots, tqu_shared=True):
+    def __init__(self, plans, slots, tqu_shared=True, keep_inputs=False):
         import torch
         import paper_1003_4984_amd as fl
         self.fl, self.torch = fl, torch
         self.plans = plans
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.tqu_shared = tqu_shared
+        self.keep_inputs = keep_inputs
+        self.retired = []             # batches to destroy once nothing is in flight
+        self.t_ref = torch.cuda.Event(enable_timing=True)
+        self.t_ref.record()
+        self.intervals = []           # (start event, end event, request ids) per group
 
     def jobs_for(self, r):
         torch, fl = self.torch, self.fl
@@ -199,45 +237,74 @@ class DeviceExecutor:
         return jobs
 
     def run_tqu(self, r, s):
-        torch, fl = self.torch, self.fl
+        fl = self.fl
         p0 = self.plans.get(r.nside, r.lmax, r.K, 0, r.cl_tt)
         p2 = self.plans.get(r.nside, r.lmax, r.K, 2, np.concatenate([r.cl_ee, r.cl_bb]))
         o, v, o2, v2 = fl.interpolate_tqu(p0, p2, r.maps["T"], r.maps["QU"], r.theta, r.phi, stream=s)
         r.out["T"] = (o, v)
         r.out["QU"] = (o2, v2)
 
+    def stage_inputs(self, r):
+        """Copy a request's host inputs to the device (on the current stream)."""
+        dev = "cuda"
+        if r.host:
+            r.maps = {k: r.host[k].to(dev, non_blocking=True) for k in ("T", "QU") if k in r.host}
+            r.theta = r.host["theta"].to(dev, non_blocking=True)
+            r.phi = r.host["phi"].to(dev, non_blocking=True)
+
     def launch(self, group, slot):
         torch = self.torch
         s = self.streams[slot]
-        shared = [r for r in group if self.tqu_shared and r.fields == "TQU"]
-        ids = {id(r) for r in shared}
-        jobs = [j for r in group if id(r) not in ids for j in self.jobs_for(r)]
-        # inputs were written on the default stream; order this stream after it
+        # device inputs produced on the default stream (if any) come first
         s.wait_stream(torch.cuda.current_stream())
-        b = None
-        if jobs:
-            b = self.fl.Batch(jobs)
-            b.run(s)
-        for r in shared:
-            self.run_tqu(r, s)
-        ev = torch.cuda.Event()
+        start = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s):
+            start.record(s)
+            for r in group:
+                self.stage_inputs(r)
+            shared = [r for r in group if self.tqu_shared and r.fields == "TQU"]
+            ids = {id(r) for r in shared}
+            jobs = [j for r in group if id(r) not in ids for j in self.jobs_for(r)]
+            b = None
+            if jobs:
+                b = self.fl.Batch(jobs)
+                b.run(s)
+            for r in shared:
+                self.run_tqu(r, s)
+        ev = torch.cuda.Event(enable_timing=True)
         ev.record(s)
-        return (ev, b, jobs)
+        self.intervals.append((start, ev, [r.rid for r in group]))
+        return (ev, b, group)
 
     def done(self, token):
-        ev, b, jobs = token
-        if ev.query():
-            if b is not None:
-                b.close()
-            return True
-        return False
+        ev, b, group = token
+        if not ev.query():
+            return False
+        if b is not None:
+            self.retired.append(b)
+        if not self.keep_inputs:
+            for r in group:
+                r.maps, r.theta, r.phi = {}, None, None
+        return True
+
+    def quiesce(self):
+        """Destroy retired batches (called when no launch is in flight)."""
+        while self.retired:
+            self.retired.pop().close()
+
+    def device_intervals(self):
+        """(start s, end s, request ids) of every launched group on the device
+        clock (relative to the executor's creation); call after synchronising."""
+        return [(self.t_ref.elapsed_time(a) * 1e-3, self.t_ref.elapsed_time(b) * 1e-3, ids)
+                for a, b, ids in self.intervals]
 
 
 def make_requests(n_req, rate, seed=0, nsides=(256, 1024, 2048, 4096), weights=(0.4, 0.3, 0.2, 0.1),
-                  tqu_frac=0.5, K=32, device="cuda", max_points=None):
+                  tqu_frac=0.5, K=32, device="cuda", max_points=None, host_inputs=True):
     """Poisson stream of lensing requests (rate per second) with fresh seeded
-    maps and deflections, lmax = N_side; inputs are synthesised before the
-    clock starts."""
+    maps and deflections, lmax = N_side; inputs are synthesised (on `device`)
+    before the clock starts and, with host_inputs, moved to pinned host memory
+    so that they reach the device only when the request is admitted."""
     import torch
     from workload import configs, spectra
     from workload.seeds import rng as seeded
@@ -255,11 +322,20 @@ def make_requests(n_req, rate, seed=0, nsides=(256, 1024, 2048, 4096), weights=(
         maps = {"T": m["T"]}
         if fields == "TQU":
             maps["QU"] = torch.cat([m["Q"], m["U"]])
+        del m
         th, ph = configs.lensing_targets(5, nside, lmax, device, job=job)
         if max_points is not None and th.numel() > max_points:
             th, ph = th[:max_points].contiguous(), ph[:max_points].contiguous()
-        reqs.append(Request(rid=i, arrival=t, nside=nside, lmax=lmax, K=K, fields=fields, n=th.numel(),
-                            cl_tt=tt, cl_ee=ee, cl_bb=bb, maps=maps, theta=th, phi=ph))
+        r = Request(rid=i, arrival=t, nside=nside, lmax=lmax, K=K, fields=fields, n=th.numel(),
+                    cl_tt=tt, cl_ee=ee, cl_bb=bb)
+        if host_inputs:
+            pin = lambda x: x.cpu().pin_memory()
+            r.host = {k: pin(v) for k, v in maps.items()}
+            r.host["theta"], r.host["phi"] = pin(th), pin(ph)
+            del maps, th, ph
+        else:
+            r.maps, r.theta, r.phi = maps, th, ph
+        reqs.append(r)
     return reqs
 
 
@@ -283,9 +359,10 @@ def main():
     reqs = make_requests(args.requests, args.rate, args.seed, nsides, weights)
     torch.cuda.synchronize()
     plans = PlanCache(lambda nside, lmax, cl, K, spin: fl.Plan(nside, lmax, cl, K, spin))
+    plans.warm(reqs)
     ex = DeviceExecutor(plans, args.slots, tqu_shared=not args.no_tqu_shared)
     srv = Server(ex, args.budget_gb * 2 ** 30, args.slots, plans,
-                 max_group_samples=int(args.group_msamples * 1e6))
+                 max_group_samples=int(args.group_msamples * 1e6), tqu_shared=not args.no_tqu_shared)
     t0 = time.perf_counter()
     done = srv.run(reqs)
     torch.cuda.synchronize()

@@ -5,16 +5,22 @@
   flints_interpolate_tqu on a seeded 1e5-target subset, 300 of them compared
   element by element with the FP64 oracle.  Tolerances: the target contract
   (values 2e-4 of the rms value, L-infinity; variances 1e-2 relative), plus the
-  tighter bound this FP64 path meets at this shape (values 1e-6; variances
-  2e-3).  The variance 1 - b^T (S + nI)^-1 b is ~6e-9 sigma0^2 here, so the
-  ~1e-12 accuracy of the tabulated correlation function, amplified by the
-  weights, bounds its relative agreement at a few 1e-4.
+  tighter bounds FP64 arithmetic gives at this shape (values 5e-7; variances
+  2e-3).
 * N_side 512, lmax 1024, K 24, T + Q + U: every lensed pixel centre through
-  flints_interpolate_tqu, 2000 compared at the FP64 tolerances of the small
-  shapes (values 1e-8, variances 1e-4 relative + 1e-9 sigma0^2).
+  flints_interpolate_tqu, 2000 compared at FP64 bounds (values 5e-7, variances
+  1e-4 relative + 1e-9 sigma0^2).
+Where the FP64 bounds come from: the GPU interpolates a correlation table
+accurate to ~1e-12 of its zero-lag value, the oracle sums the series exactly
+per pair.  Perturbing S and b by 1e-12 in the oracle moves the spin-2 values by
+6e-8 to 9e-8 of their rms at these shapes (S + nI has condition numbers up to
+2e9 with K = 24..32 at one pixel spacing) and the variances by 3e-6 (N_side
+512) to 4e-4 (N_side 4096, where the variance is ~6e-9 sigma0^2, a
+cancellation); the bounds leave a factor of about five.
 * The 2^24-target chunks of the shared-stencil call: n = 2^24 + 4097 targets
   at N_side 1024, K 32; shared equals separate bit for bit everywhere, and
-  oracle samples straddle the chunk boundary and the ragged tail.
+  oracle samples straddle the chunk boundary and the ragged tail (FP64 bounds
+  as at N_side 512).
 """
 import numpy as np
 import pytest
@@ -112,7 +118,7 @@ def test_parity_nside4096_tqu(cfg3):
         e, ev = _errors(gv, gw, ov, ow)
         res[f] = (e, ev)
         assert e <= 2e-4 and ev <= 1e-2, (f, e, ev)      # target contract
-        assert e <= 1e-6 and ev <= 2e-3, (f, e, ev)      # what FP64 reaches here
+        assert e <= 5e-7 and ev <= 2e-3, (f, e, ev)      # FP64 bound at this shape
     _log("cfg3 parity (value L-inf / rms, variance max rel): " +
          ", ".join(f"{f} {e:.2e} {ev:.2e}" for f, (e, ev) in res.items()))
 
@@ -137,8 +143,8 @@ def test_parity_nside512_tqu(gpu_ok):
     g0, gw0 = o0.cpu().numpy()[pick], v0.cpu().numpy()[pick]
     g2 = o2.cpu().numpy().reshape(2, n).T[pick]
     gw2 = v2.cpu().numpy().reshape(2, n).T[pick]
-    compare(g0, gw0, ov0, ow0, 1e-8, 1e-4, 1e-9 * p0.info()["sigma2"])
-    compare(g2, gw2, ov2, ow2, 1e-8, 1e-4, 1e-9 * p2.info()["sigma2"])
+    compare(g0, gw0, ov0, ow0, 5e-7, 1e-4, 1e-9 * p0.info()["sigma2"])
+    compare(g2, gw2, ov2, ow2, 5e-7, 1e-4, 1e-9 * p2.info()["sigma2"])
     _log("cfg2 parity (value L-inf / rms, variance max rel): "
          f"T {_errors(g0, gw0, ov0, ow0)}, Q {_errors(g2[:, 0], gw2[:, 0], ov2[:, 0], ow2[:, 0])}, "
          f"U {_errors(g2[:, 1], gw2[:, 1], ov2[:, 1], ow2[:, 1])}")
@@ -175,5 +181,5 @@ def test_tqu_chunk_boundary(gpu_ok):
     g0, gw0 = r0.cpu().numpy()[pick], rv0.cpu().numpy()[pick]
     g2 = r2.cpu().numpy().reshape(2, n).T[pick]
     gw2 = rv2.cpu().numpy().reshape(2, n).T[pick]
-    compare(g0, gw0, ov0, ow0, 1e-8, 1e-4, 1e-9 * p0.info()["sigma2"])
-    compare(g2, gw2, ov2, ow2, 1e-8, 1e-4, 1e-9 * p2.info()["sigma2"])
+    compare(g0, gw0, ov0, ow0, 5e-7, 1e-4, 1e-9 * p0.info()["sigma2"])
+    compare(g2, gw2, ov2, ow2, 5e-7, 1e-4, 1e-9 * p2.info()["sigma2"])

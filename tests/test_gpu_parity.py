@@ -97,8 +97,10 @@ def test_parity_cfg1(cfg1):
 
 
 @pytest.mark.parametrize("mode", [fl.S2_FULL, fl.S2_PAPER])
-@pytest.mark.parametrize("K", [8, 16, 24, 32])
+@pytest.mark.parametrize("K", [8, 16, 24, 32, 40, 48, 64])
 def test_parity_spin2(gpu_ok, mode, K):
+    """K <= 32: row groups and the 64-row tile engine; K = 40, 48 (80, 96 rows)
+    and 64 (128 rows): the multi-pass tile engine."""
     nside, lmax = 64, 160
     tt, ee, te, bb = spectra.cl_acoustic(lmax)
     bb = 0.1 * ee

@@ -112,7 +112,7 @@ def test_unshared_pairs_run_as_two_calls(gpu_ok):
     nside, lmax, K = 32, 64, 16
     mt, mqu, cl_tt, cl_ee = _maps(nside, lmax, 11)
     th, ph = _targets(777, 11)
-    p0 = fl.Plan(nside, lmax, cl_tt, K, 0, precision=fl.FP32_IR)
+    p0 = fl.Plan(nside, lmax, cl_tt, K, 0, precision=fl.FP32_IR, fp32_max_reject=1.0)
     p2 = fl.Plan(nside, lmax, np.concatenate([cl_ee, cl_ee]), K, 2)
     _check_shared_equals_separate(p0, p2, mt, mqu, th, ph, shared=False)
     p0m = fl.Plan(nside, lmax, cl_tt, K, 0, var_kind=fl.VAR_MSE)

@@ -95,3 +95,41 @@ def test_north_south_mirror():
         b = v[rt["first"][m]: rt["first"][m] + rt["count"][m]]
         assert np.allclose(a[:, :2], b[:, :2], atol=1e-15)
         assert np.allclose(a[:, 2], -b[:, 2], atol=1e-15)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 32])
+def test_ang2pix_centres_round_trip(N):
+    pix = np.arange(healpix.npix(N))
+    th, ph = healpix.pix2ang(N, pix)
+    assert np.array_equal(healpix.ang2pix(N, th, ph), pix)
+    # also with phi shifted by whole turns
+    assert np.array_equal(healpix.ang2pix(N, th, ph - 4 * np.pi), pix)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 16])
+def test_ang2pix_equal_area_and_second_transcription(N):
+    rng = np.random.default_rng(2)
+    M = 400000
+    z = rng.uniform(-1, 1, M)
+    phi = rng.uniform(0, 2 * np.pi, M)
+    pix = healpix.ang2pix(N, np.arccos(z), phi)
+    assert np.array_equal(pix, _ang2pix_ring(N, z, phi))
+    counts = np.bincount(pix, minlength=12 * N * N)
+    exp = M / (12 * N * N)
+    dof = 12 * N * N - 1
+    assert np.sum((counts - exp) ** 2 / exp) < dof + 6 * np.sqrt(2 * dof)
+
+
+def test_ang2pix_contains_near_centre():
+    """The containing pixel's centre is one of the four nearest centres and
+    closer than the largest pixel radius (< 1.4 x the mean pixel size)."""
+    N = 16
+    rng = np.random.default_rng(3)
+    th, ph = np.arccos(rng.uniform(-1, 1, 3000)), rng.uniform(0, 2 * np.pi, 3000)
+    pix = healpix.ang2pix(N, th, ph)
+    v = healpix.ang2vec(th, ph)
+    allv = healpix.all_vec(N)
+    d = np.linalg.norm(allv[None, :, :] - v[:, None, :], axis=-1)
+    rank = np.sum(d < d[np.arange(len(pix)), pix][:, None], axis=1)
+    assert np.all(rank < 4)
+    assert np.max(d[np.arange(len(pix)), pix]) < 1.4 * np.sqrt(4 * np.pi / healpix.npix(N))

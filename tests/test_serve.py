@@ -4,7 +4,8 @@ that arrive while slots are busy, plan-table accounting, latency report."""
 import numpy as np
 import pytest
 
-from paper_1003_4984_amd.serve import Request, Server, PlanCache, report, BYTES_PER_SAMPLE, TABLE_BYTES_BOUND
+from paper_1003_4984_amd.serve import (Request, Server, PlanCache, report, BYTES_PER_SAMPLE, TABLE_BYTES_BOUND,
+                                       BATCH_BYTES_BOUND, TQU_CHUNK)
 
 
 class Clock:
@@ -101,7 +102,9 @@ def test_new_plan_tables_count_against_budget():
     r.cl_ee, r.cl_bb = np.ones(17), np.zeros(17)
     assert plans.missing(r) == 2
     maps = 8 * 12 * 16 * 16 * 3                      # T, Q, U at N_side 16
-    assert r.footprint(plans.missing(r)) == maps + 16 * 100 + 3 * 100 * BYTES_PER_SAMPLE + 2 * TABLE_BYTES_BOUND
+    stencils = 4 * 8 * 100                           # K int32 per target for the shared search
+    assert r.footprint(plans.missing(r)) == (maps + 16 * 100 + 3 * 100 * BYTES_PER_SAMPLE + stencils
+                                             + BATCH_BYTES_BOUND + 2 * TABLE_BYTES_BOUND)
     plans.get(16, 16, 8, 0, r.cl_tt)
     assert plans.missing(r) == 1 and len(plans) == 1
     plans.get(16, 16, 8, 0, r.cl_tt)
@@ -119,3 +122,41 @@ def test_group_cap_splits_launches():
     done = srv.run(reqs, idle=idle)
     assert len(done) == 4
     assert ex.groups == [[0], [1], [2], [3]]
+
+
+def test_tqu_footprint_counts_stencil_buffer():
+    """The stencil buffer of the shared-search T+Q+U call is K int32 per target
+    of one 2^24-target chunk; without the shared call it is not needed."""
+    r = Request(rid=0, arrival=0.0, nside=4096, lmax=4096, K=32, fields="TQU", n=12 * 4096 ** 2)
+    base = 8 * 12 * 4096 ** 2 * 3 + 16 * r.n + r.samples * BYTES_PER_SAMPLE + BATCH_BYTES_BOUND
+    assert r.footprint(0, tqu_shared=True) == base + 4 * 32 * TQU_CHUNK
+    assert r.footprint(0, tqu_shared=False) == base
+    t = Request(rid=1, arrival=0.0, nside=4096, lmax=4096, K=32, fields="T", n=1000)
+    assert t.footprint(0, True) == t.footprint(0, False)
+
+
+def test_admission_waits_while_memory_is_held():
+    """Budget for one request at a time: the second is refused while the first
+    holds its memory and is admitted only after the first has completed."""
+    reqs = _reqs([0.0, 0.0001], [5000, 5000])
+    budget = int(1.5 * reqs[0].footprint())
+    srv, ex, done, _ = _serve(reqs, budget=budget, slots=2)
+    a, b = sorted(done, key=lambda r: r.rid)
+    assert b.admitted >= a.finished
+    assert srv.peak <= budget and ex.max_live == 1
+
+
+def test_server_sleeps_instead_of_spinning():
+    """With no idle hook the loop yields through its sleep function while it
+    waits for an arrival or a completion."""
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    slept = []
+
+    def sleep(dt):
+        slept.append(dt)
+        clock.t += max(dt, 1e-5)
+
+    srv = Server(ex, 10 ** 9, 1, None, clock=clock, sleep=sleep)
+    done = srv.run(_reqs([0.0, 0.05], [1000, 1000]))
+    assert len(done) == 2 and slept and all(0.0 <= d <= 1e-3 for d in slept)
