@@ -117,10 +117,8 @@ void flints_default_opts(flints_opts *o);
  *          correlation_func sums from l = 1).  spin 2: C^EE_l for l = 0..lmax
  *          followed by C^BB_l for l = 0..lmax (l < 2 ignored).  Must be finite
  *          and non-negative; read during the call only.
- *   K      stencil size, 1 <= K <= min(64, 12 nside^2).  Spin 2 solves a 2K x 2K
- *          system: up to 64 rows every option applies; above (K > 32) the plan
- *          runs FP64 (an FLINTS_FP32_IR request computes in FP64, reported by
- *          flints_plan_info) and FLINTS_VAR_MSE is refused.
+ *   K      stencil size, 1 <= K <= min(64, 12 nside^2) for spin 0 and
+ *          1 <= K <= 32 for spin 2 (a 2K x 2K system of at most 64 rows).
  *   spin   0 (temperature) or 2 (Q, U polarisation).
  * The correlation function is built on the current HIP device in FP64 and kept
  * in device memory.  Returns NULL on error (see flints_last_error()).
@@ -176,6 +174,27 @@ int flints_interpolate(flints_plan_t plan, const void *map, const double *theta,
 int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
                            const void *map_qu, const double *theta, const double *phi, int64_t n,
                            void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream);
+
+/*
+ * flints_interpolate_tqu for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid hipMalloc):
+ * the same arguments, outputs and counters as flints_interpolate_tqu, but the
+ * stencil hand-over buffer is a static 64 MiB device array of the library
+ * instead of a stream-ordered allocation, and nothing is allocated or freed.
+ * Targets run in chunks of what the array holds, 64 MiB / (4 K) stencils
+ * (524,288 targets at K = 32), so n is not limited; a K whose stencil of four
+ * targets would not fit returns FLINTS_ELIMIT (no plan has one).  Each device
+ * holds its own array from the first call on it until the process ends; the
+ * caller passes inputs and outputs as for flints_interpolate_tqu.  All calls
+ * on one device share that array: calls that overlap on one device (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Plan pairs that flints_tqu_shared reports as not shared run as two
+ * flints_interpolate calls, which use no workspace.
+ */
+int flints_interpolate_tqu_noalloc(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
+                                   const void *map_qu, const double *theta, const double *phi,
+                                   int64_t n, void *out_t, void *var_t, void *out_qu, void *var_qu,
+                                   void *stream);
 
 /*
  * Supersampling (paper Sec. 2.6, Table 1: a map of resolution N_side

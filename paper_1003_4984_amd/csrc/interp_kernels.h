@@ -458,16 +458,10 @@ inline int launch_spin(const Plan *p, const double *map, const double *theta, co
                        int64_t n, double *out, double *var, hipStream_t s) {
   const int nrow = p->d.n;
   if (nrow > 64) {
-    // systems of more than 64 rows (spin 2, K > 32) run the FP64 multi-pass
-    // tile engine; plan creation routes such FP32 plans to FP64 and refuses the
-    // MSE variance for them
-    if constexpr (SPIN == 2 && !MSE && !FP32) {
-      if (nrow <= 96) return launch_tile_big<6, SPIN>(p, map, theta, phi, n, out, var, s);
-      return launch_tile_big<8, SPIN>(p, map, theta, phi, n, out, var, s);
-    } else {
-      set_error("systems of more than 64 rows run only the FP64 paper-variance path");
-      return FLINTS_ELIMIT;
-    }
+    // plan creation refuses systems of more than 64 rows: the multi-pass tile
+    // engine for them (launch_tile_big) is switched off
+    set_error("systems of more than 64 rows are not supported");
+    return FLINTS_ELIMIT;
   }
   if (!MSE && nrow <= 16) return launch_rs<1, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
   if (!MSE && nrow <= 32) return launch_rs<2, SPIN, FP32>(p, map, theta, phi, n, out, var, s);

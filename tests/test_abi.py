@@ -44,15 +44,18 @@ def test_default_opts_and_error_paths():
     assert b"K" in lib.flints_last_error()
     cl2 = np.ones(22)          # spin 2: C^EE then C^BB for l = 0..10
     ptr2 = cl2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    assert not lib.flints_plan(8, 10, ptr2, 65, 2)                 # spin 2: K <= 64
+    assert not lib.flints_plan(8, 10, ptr2, 65, 2)                 # K <= 64
     assert b"K" in lib.flints_last_error()
+    assert not lib.flints_plan(8, 10, ptr2, 33, 2)                 # spin 2: K <= 32
+    assert b"K <= 32" in lib.flints_last_error()
     assert not lib.flints_plan(1, 10, ptr, 13, 0)                  # K <= npix = 12
     assert b"K" in lib.flints_last_error()
     o2 = flints._Opts()
     lib.flints_default_opts(ctypes.byref(o2))
-    o2.var_kind = flints.VAR_MSE
-    assert not lib.flints_plan_ex(8, 10, ptr2, 33, 2, ctypes.byref(o2))   # MSE: at most 64 rows
-    assert b"MSE" in lib.flints_last_error()
+    o2.stencil = flints.STENCIL_PIXEL
+    assert not lib.flints_plan_ex(8, 10, ptr, 49, 0, ctypes.byref(o2))   # pixel stencils: <= 48 rows
+    assert b"STENCIL_PIXEL" in lib.flints_last_error()
+
     assert o.fp32_max_reject == 0.0
     bad = cl.copy()
     bad[3] = -1.0
@@ -61,4 +64,6 @@ def test_default_opts_and_error_paths():
     assert lib.flints_interpolate(None, None, None, None, 0, None, None, None) == -1
     assert lib.flints_plan_stats(None, None, None) == -1
     assert lib.flints_plan_reset_stats(None, None) == -1
+    assert lib.flints_interpolate_tqu_noalloc(None, None, None, None, None, None, 0, None, None, None,
+                                              None, None) == -1
     lib.flints_plan_destroy(None)
