@@ -56,6 +56,7 @@ enum { FLINTS_S2_FULL = 0, FLINTS_S2_PAPER = 1 };
 enum { FLINTS_NUG_ALWAYS = 0, FLINTS_NUG_ON_FAILURE = 1 };
 enum { FLINTS_VAR_PAPER = 0, FLINTS_VAR_MSE = 1 };
 enum { FLINTS_STENCIL_NEAREST = 0, FLINTS_STENCIL_PIXEL = 1 };
+enum { FLINTS_MAP_F64 = 0, FLINTS_MAP_F32 = 1 };
 
 typedef struct {
   /* FLINTS_FP64: every step in double precision.
@@ -103,6 +104,11 @@ typedef struct {
    *   about N_side^2 classes x (4 K + 4 n (n + 1)) bytes (n = K or 2K) of
    *   device memory, reported by flints_plan_info. */
   int stencil;
+  /* FLINTS_MAP_F64 (default): maps hold doubles.  FLINTS_MAP_F32: maps hold
+   * floats (half the gather bytes); each value is widened to double exactly
+   * and everything else is unchanged, so the outputs equal those of an
+   * FLINTS_MAP_F64 plan given the same values as doubles. */
+  int map_type;
 } flints_opts;
 
 /* Fill *o with the defaults above. */
@@ -130,7 +136,8 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
 /*
  * Interpolate a RING map at n target directions (paper Sec. 2.5, steps 4-6).
  *   map    device, RING order.  spin 0: double[npix].  spin 2: double[2*npix],
- *          the Q plane followed by the U plane.
+ *          the Q plane followed by the U plane (float instead of double for
+ *          plans made with FLINTS_MAP_F32).
  *   theta  device double[n], colatitude in [0, pi].
  *   phi    device double[n], longitude, any real (reduced modulo 2 pi).
  *   out    device.  spin 0: double[n].  spin 2: double[2*n] = (Q[n], U[n]).
@@ -176,25 +183,11 @@ int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const vo
                            void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream);
 
 /*
- * flints_interpolate_tqu for callers that cannot allocate device memory (code
- * under HIP graph capture, tight serving loops, hosts that forbid hipMalloc):
- * the same arguments, outputs and counters as flints_interpolate_tqu, but the
- * stencil hand-over buffer is a static 64 MiB device array of the library
- * instead of a stream-ordered allocation, and nothing is allocated or freed.
- * Targets run in chunks of what the array holds, 64 MiB / (4 K) stencils
- * (524,288 targets at K = 32), so n is not limited; a K whose stencil of four
- * targets would not fit returns FLINTS_ELIMIT (no plan has one).  Each device
- * holds its own array from the first call on it until the process ends; the
- * caller passes inputs and outputs as for flints_interpolate_tqu.  All calls
- * on one device share that array: calls that overlap on one device (other
- * streams, other host threads) race and must be serialised by the caller.
- * Plan pairs that flints_tqu_shared reports as not shared run as two
- * flints_interpolate calls, which use no workspace.
+ * Centres of all RING pixels of resolution nside (the target directions of
+ * flints_supersample, computed by the same kernel):
+ *   theta, phi  device double[12 nside^2].  1 <= nside <= 16384.
  */
-int flints_interpolate_tqu_noalloc(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
-                                   const void *map_qu, const double *theta, const double *phi,
-                                   int64_t n, void *out_t, void *var_t, void *out_qu, void *var_qu,
-                                   void *stream);
+int flints_pixel_centres(int64_t nside, double *theta, double *phi, void *stream);
 
 /*
  * Supersampling (paper Sec. 2.6, Table 1: a map of resolution N_side
@@ -255,6 +248,7 @@ typedef struct {
   int64_t pixel_classes;           /* FLINTS_STENCIL_PIXEL: tabulated classes */
   int64_t class_nuggets;           /* classes whose factor needed -lambda_min + eps */
   int64_t table_bytes;             /* device bytes of the plan's tables */
+  int map_type;                    /* FLINTS_MAP_F64 or FLINTS_MAP_F32 */
 } flints_plan_info_t;
 
 int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info);

@@ -38,6 +38,7 @@ void flints_default_opts(flints_opts *o) {
   o->refine_tol = 0.0;
   o->fp32_max_reject = 0.0;
   o->stencil = FLINTS_STENCIL_NEAREST;
+  o->map_type = FLINTS_MAP_F64;
 }
 
 const char *flints_last_error(void) { return g_last_error.c_str(); }
@@ -76,6 +77,7 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
   if (o.nugget != FLINTS_NUG_ALWAYS && o.nugget != FLINTS_NUG_ON_FAILURE) { set_error("bad nugget policy"); return nullptr; }
   if (o.var_kind != FLINTS_VAR_PAPER && o.var_kind != FLINTS_VAR_MSE) { set_error("bad var_kind"); return nullptr; }
   if (o.stencil != FLINTS_STENCIL_NEAREST && o.stencil != FLINTS_STENCIL_PIXEL) { set_error("bad stencil"); return nullptr; }
+  if (o.map_type != FLINTS_MAP_F64 && o.map_type != FLINTS_MAP_F32) { set_error("bad map_type"); return nullptr; }
   if (o.stencil == FLINTS_STENCIL_PIXEL) {
     if ((spin == 0 && K > 48) || (spin == 2 && K > 16)) {
       set_error("FLINTS_STENCIL_PIXEL supports at most 48 rows (spin 0: K <= 48, spin 2: K <= 16)");
@@ -163,6 +165,7 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
   }
   d.counters = p->d_counters;
   d.stencil_mode = o.stencil;
+  d.map_f32 = o.map_type == FLINTS_MAP_F32 ? 1 : 0;
   if (o.stencil == FLINTS_STENCIL_PIXEL) {
     d.precision = FLINTS_FP64;           // the tabulated factors are FP64
     if (build_fixed(p) != FLINTS_OK) {
@@ -229,17 +232,11 @@ int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const vo
                                 (double *)out_qu, (double *)var_qu, (hipStream_t)stream);
 }
 
-int flints_interpolate_tqu_noalloc(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
-                                   const void *map_qu, const double *theta, const double *phi,
-                                   int64_t n, void *out_t, void *var_t, void *out_qu, void *var_qu,
-                                   void *stream) {
+int flints_pixel_centres(int64_t nside, double *theta, double *phi, void *stream) {
   g_last_error.clear();
-  const int rc = check_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, n, out_t, out_qu);
-  if (rc != FLINTS_OK || n == 0) return rc;
-  return launch_interpolate_tqu_noalloc(as_plan(plan_t), as_plan(plan_qu), (const double *)map_t,
-                                        (const double *)map_qu, theta, phi, n, (double *)out_t,
-                                        (double *)var_t, (double *)out_qu, (double *)var_qu,
-                                        (hipStream_t)stream);
+  if (nside < 1 || nside > 16384) { set_error("nside must be in [1, 16384]"); return FLINTS_EINVAL; }
+  if (!theta || !phi) { set_error("theta and phi must be non-NULL"); return FLINTS_EINVAL; }
+  return launch_pixel_centres(nside, theta, phi, (hipStream_t)stream);
 }
 
 int flints_supersample(flints_plan_t plan, const void *map, int64_t nside_out, void *out, void *var,
@@ -298,6 +295,7 @@ int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info) {
   info->precision = p->d.precision;
   info->fp32_probe_reject = p->fp32_reject;
   info->stencil = p->d.stencil_mode;
+  info->map_type = p->d.map_f32 ? FLINTS_MAP_F32 : FLINTS_MAP_F64;
   info->pixel_classes = p->nclass;
   info->class_nuggets = p->class_nuggets;
   info->table_bytes = (int64_t)p->d.ntab * p->d.nfun * 8 +

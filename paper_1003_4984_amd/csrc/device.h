@@ -336,6 +336,12 @@ __device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, dou
 // the target in the target's (e_theta, e_phi, z) frame (0-2), the point's own
 // e_theta (3-5) and e_phi (6-7) in that frame, gathered map values (8-9).
 
+// Map value i (float32 maps are widened exactly); zero without a map.
+__device__ __forceinline__ double map_value(const PlanDev &P, const double *__restrict__ map, int64_t i) {
+  if (!map) return 0.0;
+  return P.map_f32 ? (double)((const float *)map)[i] : map[i];
+}
+
 template <int SPIN>
 __device__ void neighbour_records(const PlanDev &P, double th, double ph, int lane, const int *sel,
                                   double *nb, const double *__restrict__ map) {
@@ -365,8 +371,8 @@ __device__ void neighbour_records(const PlanDev &P, double th, double ph, int la
       f[2] = R.z - zt;
       f[3] = R.z * cd; f[4] = R.z * sd; f[5] = -R.s;
       f[6] = -sd;      f[7] = cd;
-      f[8] = map ? map[p] : 0.0;                      // no map: the conditioning probe
-      f[9] = (SPIN == 2 && map) ? map[P.npix + p] : 0.0;
+      f[8] = map_value(P, map, p);                     // no map: the conditioning probe
+      f[9] = (SPIN == 2) ? map_value(P, map, P.npix + p) : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < NBF; ++i) nb[i * ns + a] = f[i];

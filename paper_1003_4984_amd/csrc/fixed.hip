@@ -429,14 +429,14 @@ __global__ __launch_bounds__(FIXED_TPB) void k_fixed(PlanDev P, const double *__
                                           cd, zt, st, c);
         if (SPIN == 0) {
           b[0][k] = c[0];
-          dv[k] = map[p];
+          dv[k] = map_value(P, map, p);
         } else {
           b[0][2 * k] = c[0];
           b[0][2 * k + 1] = c[2];
           b[NB - 1][2 * k] = c[1];
           b[NB - 1][2 * k + 1] = c[3];
-          dv[2 * k] = map[p];
-          dv[2 * k + 1] = map[P.npix + p];
+          dv[2 * k] = map_value(P, map, p);
+          dv[2 * k + 1] = map_value(P, map, P.npix + p);
         }
       }
     }

@@ -37,6 +37,8 @@ struct PlanDev {
   // Cholesky factor of S + n I (packed rows, 1 / L_ii on the diagonal).
   int32_t stencil_mode;
   int32_t lsz;         // doubles per class factor, n (n + 1) / 2
+  int32_t map_f32;     // maps hold float32 values (read and widened to FP64)
+  int32_t pad_;
   const int64_t *cls_base;   // [4 nside] (index by ring)
   const int32_t *cls_quad;   // [4 nside]
   const int32_t *cls_stn;    // [nclass][K]
@@ -71,10 +73,6 @@ int launch_interpolate(const Plan *p, const double *map, const double *theta, co
 int launch_interpolate_tqu(const Plan *p0, const Plan *p2, const double *map0, const double *map2,
                            const double *theta, const double *phi, int64_t n, double *out0,
                            double *var0, double *out2, double *var2, hipStream_t s);
-int launch_interpolate_tqu_noalloc(const Plan *p0, const Plan *p2, const double *map0,
-                                   const double *map2, const double *theta, const double *phi,
-                                   int64_t n, double *out0, double *var0, double *out2, double *var2,
-                                   hipStream_t s);
 bool tqu_shareable(const Plan *p0, const Plan *p2, const double *var0, const double *var2);
 int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_t n,
                    int64_t *idx, hipStream_t s);
@@ -85,6 +83,7 @@ hipMemPool_t workspace_pool();
 // Supersampling (supersample.hip): every pixel centre of a RING map of nside_out.
 int launch_supersample(const Plan *p, const double *map, int64_t nside_out, double *out, double *var,
                        hipStream_t s);
+int launch_pixel_centres(int64_t nside, double *theta, double *phi, hipStream_t s);
 // Fixed-stencil tables (fixed.hip): classes, representative stencils and
 // factors; and the per-target and stencil launchers of that mode.
 int build_fixed(Plan *p);

@@ -21,6 +21,19 @@ __global__ void k_pixel_centres(int64_t N, int64_t n, double *__restrict__ theta
   }
 }
 
+int launch_pixel_centres(int64_t nside, double *theta, double *phi, hipStream_t s) {
+  const int64_t n = 12 * nside * nside;
+  const int threads = 256;
+  const int64_t blocks = std::min<int64_t>((n + threads - 1) / threads, 65536);
+  hipLaunchKernelGGL(k_pixel_centres, dim3((unsigned)blocks), dim3(threads), 0, s, nside, n, theta, phi);
+  const hipError_t le = hipGetLastError();
+  if (le != hipSuccess) {
+    set_error(std::string("pixel-centre kernel launch failed: ") + hipGetErrorString(le));
+    return FLINTS_EDEVICE;
+  }
+  return FLINTS_OK;
+}
+
 int launch_supersample(const Plan *p, const double *map, int64_t nside_out, double *out, double *var,
                        hipStream_t s) {
   const int64_t n = 12 * nside_out * nside_out;
@@ -34,18 +47,8 @@ int launch_supersample(const Plan *p, const double *map, int64_t nside_out, doub
     set_error("workspace allocation for the output pixel centres failed");
     return FLINTS_ENOMEM;
   }
-  const int threads = 256;
-  const int64_t blocks = std::min<int64_t>((n + threads - 1) / threads, 65536);
-  hipLaunchKernelGGL(k_pixel_centres, dim3((unsigned)blocks), dim3(threads), 0, s, nside_out, n, dir,
-                     dir + n);
-  const hipError_t le = hipGetLastError();
-  int rc = FLINTS_OK;
-  if (le != hipSuccess) {
-    set_error(std::string("pixel-centre kernel launch failed: ") + hipGetErrorString(le));
-    rc = FLINTS_EDEVICE;
-  } else {
-    rc = launch_interpolate(p, map, dir, dir + n, n, out, var, s);
-  }
+  int rc = launch_pixel_centres(nside_out, dir, dir + n, s);
+  if (rc == FLINTS_OK) rc = launch_interpolate(p, map, dir, dir + n, n, out, var, s);
   (void)hipFreeAsync(dir, s);
   return rc;
 }

@@ -17,6 +17,7 @@ S2_FULL, S2_PAPER = 0, 1
 NUG_ALWAYS, NUG_ON_FAILURE = 0, 1
 VAR_PAPER, VAR_MSE = 0, 1
 STENCIL_NEAREST, STENCIL_PIXEL = 0, 1
+MAP_F64, MAP_F32 = 0, 1
 
 _lib = None
 
@@ -30,7 +31,7 @@ class _Opts(ctypes.Structure):
                 ("nugget", ctypes.c_int), ("var_kind", ctypes.c_int),
                 ("table_tol", ctypes.c_double), ("pivot_ratio_min", ctypes.c_double),
                 ("refine_tol", ctypes.c_double), ("fp32_max_reject", ctypes.c_double),
-                ("stencil", ctypes.c_int)]
+                ("stencil", ctypes.c_int), ("map_type", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -41,7 +42,8 @@ class _Info(ctypes.Structure):
                 ("search_rcap", ctypes.c_double), ("nugget_eps", ctypes.c_double),
                 ("precision", ctypes.c_int), ("fp32_probe_reject", ctypes.c_double),
                 ("stencil", ctypes.c_int), ("pixel_classes", ctypes.c_int64),
-                ("class_nuggets", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
+                ("class_nuggets", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
+                ("map_type", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -65,8 +67,8 @@ class _BatchInfo(ctypes.Structure):
 BATCH_AUTOTUNE = 1
 
 EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
-           "flints_interpolate_tqu", "flints_interpolate_tqu_noalloc", "flints_tqu_shared",
-           "flints_supersample",
+           "flints_interpolate_tqu", "flints_tqu_shared",
+           "flints_supersample", "flints_pixel_centres",
            "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
            "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error",
            "flints_batch_create", "flints_batch_run", "flints_batch_capture", "flints_batch_info",
@@ -93,8 +95,8 @@ def load_library(path=LIB_PATH):
     lib.flints_interpolate.restype = c_int
     lib.flints_interpolate_tqu.argtypes = [vp, vp, dp, dp, dp, dp, i64, dp, dp, dp, dp, vp]
     lib.flints_interpolate_tqu.restype = c_int
-    lib.flints_interpolate_tqu_noalloc.argtypes = [vp, vp, dp, dp, dp, dp, i64, dp, dp, dp, dp, vp]
-    lib.flints_interpolate_tqu_noalloc.restype = c_int
+    lib.flints_pixel_centres.argtypes = [i64, dp, dp, vp]
+    lib.flints_pixel_centres.restype = c_int
     lib.flints_supersample.argtypes = [vp, dp, i64, dp, dp, vp]
     lib.flints_supersample.restype = c_int
     lib.flints_tqu_shared.argtypes = [vp, vp, c_int, c_int]
@@ -161,7 +163,8 @@ class Plan:
 
     def __init__(self, nside, lmax, cl, K, spin, precision=FP64, spin2_mode=S2_FULL,
                  nugget=NUG_ALWAYS, var_kind=VAR_PAPER, table_tol=0.0,
-                 pivot_ratio_min=0.0, refine_tol=0.0, fp32_max_reject=0.0, stencil=STENCIL_NEAREST):
+                 pivot_ratio_min=0.0, refine_tol=0.0, fp32_max_reject=0.0, stencil=STENCIL_NEAREST,
+                 map_type=MAP_F64):
         lib = load_library()
         cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64).ravel())
         need = (lmax + 1) * (1 if spin == 0 else 2)
@@ -173,6 +176,7 @@ class Plan:
         o.table_tol, o.pivot_ratio_min, o.refine_tol = table_tol, pivot_ratio_min, refine_tol
         o.fp32_max_reject = fp32_max_reject
         o.stencil = stencil
+        o.map_type = map_type
         h = lib.flints_plan_ex(int(nside), int(lmax), cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                int(K), int(spin), ctypes.byref(o))
         if not h:
@@ -181,6 +185,12 @@ class Plan:
         self.nside, self.lmax, self.K, self.spin = int(nside), int(lmax), int(K), int(spin)
         self.npix = 12 * self.nside * self.nside
         self.nfield = 1 if spin == 0 else 2
+        self.map_type = int(map_type)
+
+    @property
+    def map_dtype(self):
+        import torch
+        return torch.float32 if self.map_type == MAP_F32 else torch.float64
 
     @property
     def handle(self):
@@ -229,7 +239,7 @@ def interpolate(plan, map_, theta, phi, out=None, var=None, want_var=True, strea
     if out.numel() != plan.nfield * n or (var is not None and var.numel() != plan.nfield * n):
         raise FlintsError("out/var have the wrong size")
     lib = plan._lib
-    rc = lib.flints_interpolate(plan.handle, _ptr(map_, "map", torch.float64),
+    rc = lib.flints_interpolate(plan.handle, _ptr(map_, "map", plan.map_dtype),
                                 _ptr(theta, "theta", torch.float64), _ptr(phi, "phi", torch.float64),
                                 int(n), _ptr(out, "out", torch.float64),
                                 _ptr(var, "var", torch.float64), _stream(stream))
@@ -238,11 +248,9 @@ def interpolate(plan, map_, theta, phi, out=None, var=None, want_var=True, strea
 
 
 def interpolate_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, out_t=None, var_t=None, out_qu=None,
-                    var_qu=None, want_var=True, stream=None, noalloc=False):
+                    var_qu=None, want_var=True, stream=None):
     """T and Q/U at the same targets with one stencil search per target
-    (flints_interpolate_tqu, or with noalloc=True flints_interpolate_tqu_noalloc,
-    whose stencil buffer is the library's static device workspace).  Returns
-    (out_t, var_t, out_qu, var_qu)."""
+    (flints_interpolate_tqu).  Returns (out_t, var_t, out_qu, var_qu)."""
     import torch
     n = theta.numel()
     if phi.numel() != n:
@@ -264,13 +272,13 @@ def interpolate_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, out_t=None, var_
             or (var_qu is not None and var_qu.numel() != 2 * n)):
         raise FlintsError("outputs have the wrong size")
     lib = plan_t._lib
-    fn = lib.flints_interpolate_tqu_noalloc if noalloc else lib.flints_interpolate_tqu
-    rc = fn(plan_t.handle, plan_qu.handle, _ptr(map_t, "map_t", torch.float64),
-            _ptr(map_qu, "map_qu", torch.float64), _ptr(theta, "theta", torch.float64),
+    fn = lib.flints_interpolate_tqu
+    rc = fn(plan_t.handle, plan_qu.handle, _ptr(map_t, "map_t", plan_t.map_dtype),
+            _ptr(map_qu, "map_qu", plan_qu.map_dtype), _ptr(theta, "theta", torch.float64),
             _ptr(phi, "phi", torch.float64), int(n), _ptr(out_t, "out_t", torch.float64),
             _ptr(var_t, "var_t", torch.float64), _ptr(out_qu, "out_qu", torch.float64),
             _ptr(var_qu, "var_qu", torch.float64), _stream(stream))
-    _check(lib, rc, "flints_interpolate_tqu_noalloc" if noalloc else "flints_interpolate_tqu")
+    _check(lib, rc, "flints_interpolate_tqu")
     return out_t, var_t, out_qu, var_qu
 
 
@@ -289,11 +297,25 @@ def supersample(plan, map_, nside_out, out=None, var=None, want_var=True, stream
     if out.numel() != plan.nfield * n or (var is not None and var.numel() != plan.nfield * n):
         raise FlintsError("out/var have the wrong size")
     lib = plan._lib
-    rc = lib.flints_supersample(plan.handle, _ptr(map_, "map", torch.float64), int(nside_out),
+    rc = lib.flints_supersample(plan.handle, _ptr(map_, "map", plan.map_dtype), int(nside_out),
                                 _ptr(out, "out", torch.float64), _ptr(var, "var", torch.float64),
                                 _stream(stream))
     _check(lib, rc, "flints_supersample")
     return out, var
+
+
+def pixel_centres(nside, device="cuda", stream=None):
+    """(theta, phi) of every RING pixel centre of `nside`, computed on the
+    device by the kernel flints_supersample uses for its targets."""
+    import torch
+    lib = load_library()
+    n = 12 * int(nside) * int(nside)
+    th = torch.empty(n, dtype=torch.float64, device=device)
+    ph = torch.empty(n, dtype=torch.float64, device=device)
+    rc = lib.flints_pixel_centres(int(nside), _ptr(th, "theta", torch.float64), _ptr(ph, "phi", torch.float64),
+                                  _stream(stream))
+    _check(lib, rc, "flints_pixel_centres")
+    return th, ph
 
 
 def tqu_shared(plan_t, plan_qu, with_var=True):
@@ -349,7 +371,7 @@ class Batch:
                 p = _ptr(t, name, torch.float64)
                 return None if p is None else p.value
             arr[i].plan = plan.handle.value
-            arr[i].map = addr(map_, "map")
+            arr[i].map = _ptr(map_, "map", plan.map_dtype).value
             arr[i].theta = addr(theta, "theta")
             arr[i].phi = addr(phi, "phi")
             arr[i].n = n

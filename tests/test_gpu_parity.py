@@ -215,3 +215,40 @@ def test_var_mse(gpu_ok, spin):
     g = gpu_stencil(p, th, ph)
     vo, varo, _ = _oracle_on_gpu_stencil(nside, clo, K, spin, maps, th, ph, g, var_kind="mse")
     compare(v, var, vo, varo, VAL_TOL, VAR_REL, 1e-9 * p.info()["sigma2"])
+
+
+@pytest.mark.parametrize("spin,K", [(0, 16), (0, 40), (2, 12), (2, 24)])
+def test_float_maps_equal_double_maps(gpu_ok, spin, K):
+    """FLINTS_MAP_F32: a float32 map gives exactly the outputs of an FP64-map
+    plan on the same values widened to double (the widening is exact and the
+    arithmetic after the gather is the same), for the row-group and tile
+    engines, alone and through the shared-stencil T + Q/U call."""
+    nside, lmax = 32, 80
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    rng = seeds.rng(12, spin * 100 + K, 0)
+    if spin == 0:
+        m = synth.synth(synth.draw_alm(rng, tt, lmax), 0, nside).numpy()
+        cl = tt
+    else:
+        q, u = synth.synth(-synth.draw_alm(rng, ee, lmax), 2, nside)
+        m, cl = np.concatenate([q.numpy(), u.numpy()]), np.concatenate([ee, bb])
+    m32 = torch.as_tensor(m, dtype=torch.float32, device="cuda")
+    p64 = fl.Plan(nside, lmax, cl, K, spin)
+    p32 = fl.Plan(nside, lmax, cl, K, spin, map_type=fl.MAP_F32)
+    assert p32.info()["map_type"] == fl.MAP_F32
+    th, ph = np.arccos(rng.uniform(-1, 1, 900)), rng.uniform(0, 2 * np.pi, 900)
+    a = fl.interpolate(p64, m32.double(), dev(th), dev(ph))
+    b = fl.interpolate(p32, m32, dev(th), dev(ph))
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    with pytest.raises(fl.FlintsError):
+        fl.interpolate(p32, m32.double(), dev(th), dev(ph))      # dtype follows the plan
+    if spin == 2 and K <= 32:
+        t = synth.synth(synth.draw_alm(rng, tt, lmax), 0, nside).numpy()
+        t32 = torch.as_tensor(t, dtype=torch.float32, device="cuda")
+        p0 = fl.Plan(nside, lmax, tt, K, 0)
+        p0f = fl.Plan(nside, lmax, tt, K, 0, map_type=fl.MAP_F32)
+        r64 = fl.interpolate_tqu(p0, p64, t32.double(), m32.double(), dev(th), dev(ph))
+        r32 = fl.interpolate_tqu(p0f, p32, t32, m32, dev(th), dev(ph))
+        torch.cuda.synchronize()
+        assert all(torch.equal(x, y) for x, y in zip(r64, r32))
