@@ -183,6 +183,27 @@ int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const vo
                            void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream);
 
 /*
+ * flints_interpolate_tqu for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid hipMalloc):
+ * the same arguments, outputs and counters as flints_interpolate_tqu, but the
+ * stencil hand-over buffer is a static 64 MiB device array of the library
+ * instead of a stream-ordered allocation, and nothing is allocated or freed.
+ * Targets run in chunks of what the array holds, 64 MiB / (4 K) stencils
+ * (524,288 targets at K = 32), so n is not limited; a K whose stencil of four
+ * targets would not fit returns FLINTS_ELIMIT (no plan has one).  Each device
+ * holds its own array from the first call on it until the process ends; the
+ * caller passes inputs and outputs as for flints_interpolate_tqu.  All calls
+ * on one device share that array: calls that overlap on one device (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Plan pairs that flints_tqu_shared reports as not shared run as two
+ * flints_interpolate calls, which use no workspace.
+ */
+int flints_interpolate_tqu_noalloc(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
+                                   const void *map_qu, const double *theta, const double *phi,
+                                   int64_t n, void *out_t, void *var_t, void *out_qu, void *var_qu,
+                                   void *stream);
+
+/*
  * Centres of all RING pixels of resolution nside (the target directions of
  * flints_supersample, computed by the same kernel):
  *   theta, phi  device double[12 nside^2].  1 <= nside <= 16384.

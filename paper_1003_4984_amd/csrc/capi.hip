@@ -232,6 +232,19 @@ int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const vo
                                 (double *)out_qu, (double *)var_qu, (hipStream_t)stream);
 }
 
+int flints_interpolate_tqu_noalloc(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
+                                   const void *map_qu, const double *theta, const double *phi,
+                                   int64_t n, void *out_t, void *var_t, void *out_qu, void *var_qu,
+                                   void *stream) {
+  g_last_error.clear();
+  const int rc = check_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, n, out_t, out_qu);
+  if (rc != FLINTS_OK || n == 0) return rc;
+  return launch_interpolate_tqu_noalloc(as_plan(plan_t), as_plan(plan_qu), (const double *)map_t,
+                                        (const double *)map_qu, theta, phi, n, (double *)out_t,
+                                        (double *)var_t, (double *)out_qu, (double *)var_qu,
+                                        (hipStream_t)stream);
+}
+
 int flints_pixel_centres(int64_t nside, double *theta, double *phi, void *stream) {
   g_last_error.clear();
   if (nside < 1 || nside > 16384) { set_error("nside must be in [1, 16384]"); return FLINTS_EINVAL; }

@@ -40,6 +40,39 @@ hipMemPool_t workspace_pool() {
   return pool;
 }
 
+// Workspace of flints_interpolate_tqu_noalloc: the stencil hand-over buffer in
+// a static device array (every device the library runs on holds its own copy
+// until the process ends).  Host code never uses the name `scratch` as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) int scratch[NOALLOC_SCRATCH_BYTES / sizeof(int)];
+
+static int *scratch_address() {
+  static std::mutex mu;
+  static std::map<int, int *> addr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("no current HIP device");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    set_error(std::string("device address of the static workspace: ") + hipGetErrorString(e));
+    return nullptr;
+  }
+  addr[dev] = (int *)ptr;
+  return (int *)ptr;
+}
+
+// Shared-stencil T + Q/U: per chunk the spin-2 main pass (which writes the
+// stencils) and then the spin-0 main pass (which reads them), each with the
+// layout and block size of its single-plan path; then both fix-up passes.
+// The stencil buffer is stream-ordered (allocated and freed on s); if it
+// cannot be allocated, each plan runs its own searching pass.
 template <int NT0, int NT2, int T2>
 static int launch_tqu_t(const Plan *p0, const Plan *p2, const double *map0, const double *map2,
                         const double *theta, const double *phi, int64_t n, double *out0, double *var0,
@@ -145,5 +178,30 @@ int launch_interpolate_tqu(const Plan *p0, const Plan *p2, const double *map0, c
   }
   return tqu_dispatch(p0, p2, map0, map2, theta, phi, n, out0, var0, out2, var2, s, nullptr, 0);
 }
+
+// The same call with the stencil buffer in the static workspace: targets run
+// in chunks of what it holds (64 MiB / (4 K) stencils, at least 262,144
+// targets for K <= 64), so nothing is allocated.
+int launch_interpolate_tqu_noalloc(const Plan *p0, const Plan *p2, const double *map0,
+                                   const double *map2, const double *theta, const double *phi,
+                                   int64_t n, double *out0, double *var0, double *out2, double *var2,
+                                   hipStream_t s) {
+  if (n == 0) return FLINTS_OK;
+  if (!tqu_shareable(p0, p2, var0, var2)) {
+    const int rc = launch_interpolate(p0, map0, theta, phi, n, out0, var0, s);
+    if (rc != FLINTS_OK) return rc;
+    return launch_interpolate(p2, map2, theta, phi, n, out2, var2, s);
+  }
+  const int K = p0->d.K;
+  const int64_t cap = (int64_t)(NOALLOC_SCRATCH_BYTES / (sizeof(int) * (size_t)K)) & ~int64_t(3);
+  if (cap < 4) {
+    set_error("K is too large for the static workspace of the no-allocation call");
+    return FLINTS_ELIMIT;
+  }
+  int *ws = scratch_address();
+  if (!ws) return FLINTS_EDEVICE;
+  return tqu_dispatch(p0, p2, map0, map2, theta, phi, n, out0, var0, out2, var2, s, ws, cap);
+}
+
 
 }  // namespace flints

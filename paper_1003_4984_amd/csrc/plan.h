@@ -73,6 +73,10 @@ int launch_interpolate(const Plan *p, const double *map, const double *theta, co
 int launch_interpolate_tqu(const Plan *p0, const Plan *p2, const double *map0, const double *map2,
                            const double *theta, const double *phi, int64_t n, double *out0,
                            double *var0, double *out2, double *var2, hipStream_t s);
+int launch_interpolate_tqu_noalloc(const Plan *p0, const Plan *p2, const double *map0,
+                                   const double *map2, const double *theta, const double *phi,
+                                   int64_t n, double *out0, double *var0, double *out2, double *var2,
+                                   hipStream_t s);
 bool tqu_shareable(const Plan *p0, const Plan *p2, const double *var0, const double *var2);
 int launch_stencil(const Plan *p, const double *theta, const double *phi, int64_t n,
                    int64_t *idx, hipStream_t s);

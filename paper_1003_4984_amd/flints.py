@@ -67,7 +67,7 @@ class _BatchInfo(ctypes.Structure):
 BATCH_AUTOTUNE = 1
 
 EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
-           "flints_interpolate_tqu", "flints_tqu_shared",
+           "flints_interpolate_tqu", "flints_interpolate_tqu_noalloc", "flints_tqu_shared",
            "flints_supersample", "flints_pixel_centres",
            "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
            "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error",
@@ -95,6 +95,8 @@ def load_library(path=LIB_PATH):
     lib.flints_interpolate.restype = c_int
     lib.flints_interpolate_tqu.argtypes = [vp, vp, dp, dp, dp, dp, i64, dp, dp, dp, dp, vp]
     lib.flints_interpolate_tqu.restype = c_int
+    lib.flints_interpolate_tqu_noalloc.argtypes = [vp, vp, dp, dp, dp, dp, i64, dp, dp, dp, dp, vp]
+    lib.flints_interpolate_tqu_noalloc.restype = c_int
     lib.flints_pixel_centres.argtypes = [i64, dp, dp, vp]
     lib.flints_pixel_centres.restype = c_int
     lib.flints_supersample.argtypes = [vp, dp, i64, dp, dp, vp]
@@ -248,9 +250,11 @@ def interpolate(plan, map_, theta, phi, out=None, var=None, want_var=True, strea
 
 
 def interpolate_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, out_t=None, var_t=None, out_qu=None,
-                    var_qu=None, want_var=True, stream=None):
+                    var_qu=None, want_var=True, stream=None, noalloc=False):
     """T and Q/U at the same targets with one stencil search per target
-    (flints_interpolate_tqu).  Returns (out_t, var_t, out_qu, var_qu)."""
+    (flints_interpolate_tqu, or with noalloc=True flints_interpolate_tqu_noalloc,
+    whose stencil buffer is the library's static device workspace).  Returns
+    (out_t, var_t, out_qu, var_qu)."""
     import torch
     n = theta.numel()
     if phi.numel() != n:
@@ -272,13 +276,13 @@ def interpolate_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, out_t=None, var_
             or (var_qu is not None and var_qu.numel() != 2 * n)):
         raise FlintsError("outputs have the wrong size")
     lib = plan_t._lib
-    fn = lib.flints_interpolate_tqu
+    fn = lib.flints_interpolate_tqu_noalloc if noalloc else lib.flints_interpolate_tqu
     rc = fn(plan_t.handle, plan_qu.handle, _ptr(map_t, "map_t", plan_t.map_dtype),
             _ptr(map_qu, "map_qu", plan_qu.map_dtype), _ptr(theta, "theta", torch.float64),
             _ptr(phi, "phi", torch.float64), int(n), _ptr(out_t, "out_t", torch.float64),
             _ptr(var_t, "var_t", torch.float64), _ptr(out_qu, "out_qu", torch.float64),
             _ptr(var_qu, "var_qu", torch.float64), _stream(stream))
-    _check(lib, rc, "flints_interpolate_tqu")
+    _check(lib, rc, "flints_interpolate_tqu_noalloc" if noalloc else "flints_interpolate_tqu")
     return out_t, var_t, out_qu, var_qu
 
 

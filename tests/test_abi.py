@@ -64,4 +64,6 @@ def test_default_opts_and_error_paths():
     assert lib.flints_interpolate(None, None, None, None, 0, None, None, None) == -1
     assert lib.flints_plan_stats(None, None, None) == -1
     assert lib.flints_plan_reset_stats(None, None) == -1
+    assert lib.flints_interpolate_tqu_noalloc(None, None, None, None, None, None, 0, None, None, None,
+                                              None, None) == -1
     lib.flints_plan_destroy(None)
