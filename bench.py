@@ -313,6 +313,101 @@ def leg_supersample(fl, torch):
     return res
 
 
+def _oracle_parity_on(pool, nside, K, tt, eebb, inp, th, ph, st, g0, gv0, g2, gv2):
+    """Oracle values on the GPU's own stencils st (n, K) at (th, ph) in the
+    worker pool, compared with the GPU outputs (g0, gv0: T; g2, gv2: (n, 2))."""
+    import torch
+    npix = 12 * nside * nside
+    chunks = [c for c in np.array_split(np.arange(len(th)), 32) if c.size]
+    work = []
+    for c in chunks:
+        pix = np.unique(st[c])
+        pt = torch.as_tensor(pix, device=inp["T"].device)
+        work.append((nside, K, tt, eebb, th[c], ph[c], st[c], pix, inp["T"][pt].cpu().numpy(),
+                     inp["QU"][pt].cpu().numpy(), inp["QU"][pt + npix].cpu().numpy()))
+    res = pool.map(_krige_chunk, work)
+    v0 = np.concatenate([r[0] for r in res])
+    w0 = np.concatenate([r[1] for r in res])
+    v2 = np.concatenate([r[2] for r in res])
+    w2 = np.concatenate([r[3] for r in res])
+    rel = lambda g, o: float(np.max(np.abs(g - o)) / np.sqrt(np.mean(o ** 2)))
+    vrel = lambda g, o: float(np.max(np.abs(g - o) / np.abs(o)))
+    verr = {"T": rel(g0, v0), "Q": rel(g2[:, 0], v2[:, 0]), "U": rel(g2[:, 1], v2[:, 1])}
+    werr = {"T": vrel(gv0, w0), "Q": vrel(gv2[:, 0], w2[:, 0]), "U": vrel(gv2[:, 1], w2[:, 1])}
+    ok = all(v <= VAL_TOL for v in verr.values()) and all(v <= VAR_TOL for v in werr.values())
+    return {"points": int(len(th)), "value_err_rel_rms": verr, "var_err_rel": werr, "parity_ok": bool(ok)}
+
+
+def leg_pixel_stencils(fl, torch, inp_main, pool):
+    """The paper's own scheme (stencil tied to the containing pixel, factors
+    tabulated per pixel class) at the lensing shape of its Table 2: N_side
+    4096, lmax 4096, K 9, T + Q + U at the main workload's lensed pixel centres
+    (paper: 22 min of interpolation for N_side 4096); and the supersampling
+    shape of its Table 1 (N_side 2048 -> 4096, lmax 4096, T, K 9 and 36;
+    paper: 3.3 and 19 min).  Plan times include the class tables."""
+    from workload import configs, spectra
+    res = {}
+    nside, lmax, K = 4096, 4096, 9
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    t0 = time.perf_counter()
+    p0 = fl.Plan(nside, lmax, tt, K, 0, stencil=fl.STENCIL_PIXEL)
+    p2 = fl.Plan(nside, lmax, np.concatenate([ee, bb]), K, 2, stencil=fl.STENCIL_PIXEL)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    th, ph = inp_main["theta"], inp_main["phi"]
+    n = th.numel()
+    o0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    v0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    o2 = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    v2 = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+
+    def call():
+        fl.interpolate(p0, inp_main["T"], th, ph, out=o0, var=v0)
+        fl.interpolate(p2, inp_main["QU"], th, ph, out=o2, var=v2)
+    t = _time_calls(torch, call, steps=3)
+    i0, i2 = p0.info(), p2.info()
+    r = {"workload": f"lensing remap N_side {nside} lmax {lmax} K {K} T+Q+U, stencil of the containing pixel",
+         "samples_per_s": 3.0 * n / t, "s_per_step": t, "plan_s": t_plan,
+         "pixel_classes": {"T": i0["pixel_classes"], "QU": i2["pixel_classes"]},
+         "table_gib": {"T": i0["table_bytes"] / 2 ** 30, "QU": i2["table_bytes"] / 2 ** 30},
+         "paper_cpu_s_per_step": 22 * 60,
+         "paper_context": "Table 2 interpolation time, N_side 4096 (hardware not stated)"}
+    if pool is not None:
+        sel = configs.parity_subset(3, n, 600, job=2)
+        sel_t = torch.as_tensor(sel, device="cuda")
+        ths, phs = th[sel_t].contiguous(), ph[sel_t].contiguous()
+        st = fl.stencil(p0, ths, phs).cpu().numpy()
+        g2 = torch.stack([o2[sel_t], o2[sel_t + n]], 1).cpu().numpy()
+        gv2 = torch.stack([v2[sel_t], v2[sel_t + n]], 1).cpu().numpy()
+        r["parity_sample"] = _oracle_parity_on(pool, nside, K, tt, (ee, bb), inp_main, ths.cpu().numpy(),
+                                               phs.cpu().numpy(), st, o0[sel_t].cpu().numpy(),
+                                               v0[sel_t].cpu().numpy(), g2, gv2)
+    res["lensing_tqu_K9"] = r
+    del p0, p2, o0, v0, o2, v2
+    torch.cuda.empty_cache()
+    # supersampling N_side 2048 -> 4096 (Table 1 shape)
+    ns, nout = 2048, 4096
+    m = configs.maps(3, ns, lmax, "T", "cuda")["T"]
+    npo = 12 * nout * nout
+    out = torch.empty(npo, dtype=torch.float64, device="cuda")
+    var = torch.empty(npo, dtype=torch.float64, device="cuda")
+    paper_s = {9: 3.3 * 60, 36: 19 * 60}
+    for Kk in (9, 36):
+        t0 = time.perf_counter()
+        p = fl.Plan(ns, lmax, tt, Kk, 0, stencil=fl.STENCIL_PIXEL)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        t = _time_calls(torch, lambda: fl.supersample(p, m, nout, out=out, var=var), steps=2)
+        res[f"supersample_2048_to_4096_K{Kk}"] = {
+            "samples_per_s": npo / t, "s_per_map": t, "plan_s": t_plan,
+            "pixel_classes": p.info()["pixel_classes"], "table_gib": p.info()["table_bytes"] / 2 ** 30,
+            "paper_cpu_s_per_map": paper_s[Kk],
+            "paper_context": "Table 1, one Xeon E5410 2.33 GHz core, tabulated S^-1 stencil"}
+        del p
+        torch.cuda.empty_cache()
+    return res
+
+
 def leg_serving(fl, torch, inp_main, rate=1.0, n_req=16):
     """Serving: Poisson requests (rate per second) with N_side {256, 1024, 2048,
     4096} (weights .4/.3/.2/.1), T or T+Q+U, K 32, lmax = N_side; each request
@@ -367,6 +462,7 @@ def run_legs(fl, torch, inp_main, pool, nw):
     legs = {}
     for name, fn in (("nside512_fp64_vs_fp32ir", lambda: leg_nside512(fl, torch, pool, nw)),
                      ("supersample_2048_to_4096", lambda: leg_supersample(fl, torch)),
+                     ("pixel_stencils", lambda: leg_pixel_stencils(fl, torch, inp_main, pool)),
                      ("serving_cfg5", lambda: leg_serving(fl, torch, inp_main))):
         log(f"leg {name}")
         try:
@@ -385,7 +481,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="nside4096", choices=sorted(SHAPES))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32ir"])
-    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--cpu-sample", type=int, default=6000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tqu", default="shared", choices=["shared", "separate"],
                     help="T and Q/U in one call sharing the stencil search (shared), or one "
