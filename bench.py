@@ -408,6 +408,151 @@ def leg_pixel_stencils(fl, torch, inp_main, pool):
     return res
 
 
+_LENS_ALM = None
+
+
+def _lens_alm():
+    """The seeded harmonic coefficients of the headline lensing workload
+    (T, E and the lensing potential at lmax 4096; drawn once per process)."""
+    global _LENS_ALM
+    if _LENS_ALM is None:
+        from workload import seeds, spectra
+        from workload.synth import draw_alm, draw_alm_te
+        lmax = 4096
+        tt, ee, te, bb = spectra.cl_acoustic(lmax)
+        aT, aE = draw_alm_te(seeds.rng(3, 0, seeds.STREAM_ALM), tt, ee, te, lmax)
+        plm = draw_alm(seeds.rng(3, 0, seeds.STREAM_PHI), spectra.cl_phi(lmax), lmax)
+        _LENS_ALM = (aT, aE, plm)
+    return _LENS_ALM
+
+
+def _lens_pixel_task(args):
+    """Oracle chain at one pixel of N_side 4096: the unlensed T and Q + iU at
+    its centre, grad(phi) there, the displaced direction and the exact lensed
+    T and Q + iU at it (sums over all l, m)."""
+    from oracle import healpix, lensing
+    nside, pix = args
+    aT, aE, plm = _lens_alm()
+    lmax = aT.shape[0] - 1
+    th, ph = healpix.pix2ang(nside, np.array([pix]))
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    t0 = lensing.synth_points_recurrence(0, aT, None, th, ph).real
+    p0 = lensing.synth_points_recurrence(2, -aE, None, th, ph)
+    d = lensing.synth_points_recurrence(1, -np.sqrt(ell * (ell + 1))[:, None] * plm, None, th, ph)
+    t2, p2 = lensing.lensed_directions(th, ph, d.real, d.imag)
+    t1 = lensing.synth_points_recurrence(0, aT, None, t2, p2).real
+    p1 = lensing.synth_points_recurrence(2, -aE, None, t2, p2)
+    return float(t0[0]), complex(p0[0]), complex(d[0]), float(t2[0]), float(p2[0]), float(t1[0]), complex(p1[0])
+
+
+def leg_lensing_pipeline(fl, torch, inp_main, pool, n_pix=48):
+    """The paper's total lensing time (Table 2: interpolation + unlensed map
+    synthesis + deflection map, initialisation excluded) on the device at
+    N_side 4096, lmax 4096: spin-0 and spin-2 synthesis of the unlensed T and
+    Q, U, spin-1 synthesis of grad(phi), the displaced pixel centres and T+Q/U
+    interpolation there -- with the K 32 nearest-pixel plans of the headline
+    and with the paper's K 9 pixel-tied stencils.  With the oracle pool, the
+    synthesised maps, deflections and directions are checked at sampled pixels
+    against the oracle's chain from the same coefficients, and the
+    interpolated values against the exact lensed sky there (the paper's
+    precision measure: error std and max over the map std)."""
+    from workload import spectra, configs
+    nside, lmax = 4096, 4096
+    npix = 12 * nside * nside
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    aT, aE, plm = _lens_alm()
+    tlm = torch.as_tensor(fl.alm_mmajor(aT), device="cuda")
+    elm = torch.as_tensor(fl.alm_mmajor(aE), device="cuda")
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    plm_d = torch.as_tensor(fl.alm_mmajor(plm), device="cuda")
+    t_map = torch.empty(npix, dtype=torch.float64, device="cuda")
+    qu_map = torch.empty(2 * npix, dtype=torch.float64, device="cuda")
+    defl = torch.empty(2 * npix, dtype=torch.float64, device="cuda")
+    th = torch.empty(npix, dtype=torch.float64, device="cuda")
+    ph = torch.empty(npix, dtype=torch.float64, device="cuda")
+    stages = {
+        "synth_T_s": lambda: fl.synthesize(nside, lmax, 0, tlm, out=t_map),
+        "synth_QU_s": lambda: fl.synthesize(nside, lmax, 2, elm, None, out=qu_map),
+        "synth_deflection_s": lambda: fl.synthesize(nside, lmax, 1, plm_d, out=defl),
+        "displace_s": lambda: fl.lensed_directions(nside, defl, th, ph),
+    }
+    res = {"workload": f"lensing pipeline N_side {nside} lmax {lmax}: synthesis of T, Q, U and grad(phi), "
+                       "displaced pixel centres, T+Q/U interpolation (all on the device)"}
+    for name, fn in stages.items():
+        res[name] = _time_calls(torch, fn, steps=2)
+    synth_s = res["synth_T_s"] + res["synth_QU_s"]
+    res["unlensed_map_s"] = synth_s
+    # consistency with the input generator's maps of the same seeds (not a parity claim)
+    res["max_diff_vs_input_generator"] = {
+        "T": float((t_map - inp_main["T"]).abs().max() / inp_main["T"].abs().max()),
+        "QU": float((qu_map - inp_main["QU"]).abs().max() / inp_main["QU"].abs().max())}
+    o = [torch.empty(k * npix, dtype=torch.float64, device="cuda") for k in (1, 1, 2, 2)]
+    sel = configs.parity_subset(3, npix, n_pix, job=5)
+    oracle = None
+    if pool is not None:
+        log(f"lensing pipeline: oracle chain at {sel.size} pixels")
+        oracle = pool.map(_lens_pixel_task, [(nside, int(p)) for p in sel])
+        sel_t = torch.as_tensor(sel, device="cuda")
+        ot = np.array([r[0] for r in oracle])
+        oqu = np.array([r[1] for r in oracle])
+        od = np.array([r[2] for r in oracle])
+        gt = t_map[sel_t].cpu().numpy()
+        gqu = qu_map[sel_t].cpu().numpy() + 1j * qu_map[sel_t + npix].cpu().numpy()
+        gd = defl[sel_t].cpu().numpy() + 1j * defl[sel_t + npix].cpu().numpy()
+        from oracle import healpix
+        gap = np.linalg.norm(healpix.ang2vec(th[sel_t].cpu().numpy(), ph[sel_t].cpu().numpy())
+                             - healpix.ang2vec(np.array([r[3] for r in oracle]), np.array([r[4] for r in oracle])),
+                             axis=-1)
+        res["parity_sample"] = {
+            "pixels": int(sel.size),
+            "T_max_err_rel": float(np.max(np.abs(gt - ot)) / np.max(np.abs(ot))),
+            "QU_max_err_rel": float(np.max(np.abs(gqu - oqu)) / np.max(np.abs(oqu))),
+            "deflection_max_err_rel": float(np.max(np.abs(gd - od)) / np.max(np.abs(od))),
+            "direction_max_gap_rad": float(np.max(gap)),
+            "tolerance": {"maps_rel": 1e-8, "direction_rad": 1e-12}}
+        res["parity_sample"]["parity_ok"] = bool(
+            max(res["parity_sample"]["T_max_err_rel"], res["parity_sample"]["QU_max_err_rel"],
+                res["parity_sample"]["deflection_max_err_rel"]) < 1e-8
+            and res["parity_sample"]["direction_max_gap_rad"] < 1e-12)
+        # exact lensed sky at the oracle's displaced directions; map std of the unlensed maps
+        ex_t = np.array([r[5] for r in oracle])
+        ex_qu = np.array([r[6] for r in oracle])
+        sd_t = float(inp_main["T"].std())
+        sd_p = float(inp_main["QU"].std())
+    for label, kw in (("K32_nearest", dict(K=32)), ("K9_pixel_stencil", dict(K=9, stencil=fl.STENCIL_PIXEL))):
+        K = kw.pop("K")
+        t0 = time.perf_counter()
+        p0 = fl.Plan(nside, lmax, tt, K, 0, **kw)
+        p2 = fl.Plan(nside, lmax, np.concatenate([ee, bb]), K, 2, **kw)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        call = lambda: fl.interpolate_tqu(p0, p2, t_map, qu_map, th, ph, out_t=o[0], var_t=o[1],
+                                          out_qu=o[2], var_qu=o[3])
+        t_int = _time_calls(torch, call, steps=2)
+        total = synth_s + res["synth_deflection_s"] + res["displace_s"] + t_int
+        r = {"interp_s": t_int, "plan_init_s": plan_s, "total_s": total,
+             "interp_over_unlensed_synthesis": t_int / synth_s,
+             "samples_per_s_total": 3.0 * npix / total}
+        if oracle is not None:
+            gi_t = o[0][sel_t].cpu().numpy()
+            gi_q = o[2][sel_t].cpu().numpy()
+            gi_u = o[2][sel_t + npix].cpu().numpy()
+            e_t, e_q, e_u = gi_t - ex_t, gi_q - ex_qu.real, gi_u - ex_qu.imag
+            r["precision_vs_exact_lensed"] = {
+                "pixels": int(sel.size),
+                "T": {"L2": float(np.sqrt(np.mean(e_t ** 2)) / sd_t), "Linf": float(np.max(np.abs(e_t)) / sd_t)},
+                "Q": {"L2": float(np.sqrt(np.mean(e_q ** 2)) / sd_p), "Linf": float(np.max(np.abs(e_q)) / sd_p)},
+                "U": {"L2": float(np.sqrt(np.mean(e_u ** 2)) / sd_p), "Linf": float(np.max(np.abs(e_u)) / sd_p)},
+                "note": "interpolated minus exact lensed value (all-l, m sum at the displaced direction), "
+                        "over the unlensed map std, as the paper's Table 2 precision columns"}
+        res[label] = r
+        del p0, p2
+        torch.cuda.empty_cache()
+    res["paper_context"] = {"total_s": 51 * 60, "interp_s": 22 * 60, "K": 9, "L2": 4e-4, "Linf": 3e-3,
+                            "note": "Table 2, N_side 4096, lmax 4096, T+Q+U (hardware not stated)"}
+    return res
+
+
 def leg_serving(fl, torch, inp_main, rate=1.0, n_req=16):
     """Serving: Poisson requests (rate per second) with N_side {256, 1024, 2048,
     4096} (weights .4/.3/.2/.1), T or T+Q+U, K 32, lmax = N_side; each request
@@ -463,6 +608,7 @@ def run_legs(fl, torch, inp_main, pool, nw):
     for name, fn in (("nside512_fp64_vs_fp32ir", lambda: leg_nside512(fl, torch, pool, nw)),
                      ("supersample_2048_to_4096", lambda: leg_supersample(fl, torch)),
                      ("pixel_stencils", lambda: leg_pixel_stencils(fl, torch, inp_main, pool)),
+                     ("lensing_pipeline", lambda: leg_lensing_pipeline(fl, torch, inp_main, pool)),
                      ("serving_cfg5", lambda: leg_serving(fl, torch, inp_main))):
         log(f"leg {name}")
         try:

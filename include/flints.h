@@ -229,6 +229,42 @@ int flints_pixel_centres(int64_t nside, double *theta, double *phi, void *stream
 int flints_supersample(flints_plan_t plan, const void *map, int64_t nside_out, void *out, void *var,
                        void *stream);
 
+/*
+ * Spin-s harmonic synthesis onto the RING pixel centres (the lensing pipeline
+ * of paper Sec. 3.1 makes the unlensed T, Q, U maps and the deflection
+ * d = grad(phi) this way; spin-weighted harmonics as in App. A,
+ * sY_lm = (-1)^s sqrt((2l+1)/4pi) e^{i m phi} d^l_{m,-s}(theta), Condon-Shortley
+ * phase, polarisation Q + iU = sum 2a_lm 2Y_lm with 2a_lm = -(E_lm + i B_lm)).
+ *   nside  1 <= nside <= 8192.  lmax  0 <= lmax <= 16384 (any lmax; orders
+ *          above the ring's Nyquist frequency alias as the sum itself does).
+ *   spin   0: alm = T_lm, map = T                          (device double[npix])
+ *          1: alm = phi_lm, map = (d_theta, d_phi) = grad phi (device double[2][npix])
+ *          2: alm = E_lm, blm = B_lm (NULL: B = 0), map = (Q, U) (device double[2][npix])
+ *   alm, blm  device, complex doubles interleaved (re, im), m >= 0 only, in
+ *          m-major order: (l, m) at index m (2 lmax + 3 - m) / 2 + (l - m),
+ *          (lmax+1)(lmax+2)/2 entries; the fields are real, so the m < 0
+ *          coefficients are (-1)^m conj(a_lm) and the m = 0 imaginary parts
+ *          are ignored.  blm must be NULL unless spin = 2.
+ *   map    device, written in full (planes of npix = 12 nside^2 doubles).
+ * Workspace from the library's stream-ordered pool: 16 B (spin 0) or 32 B
+ * (spin 1, 2) per (ring, m) for the ring coefficients, then per group of rings
+ * of equal transform length two complex buffers of that length per ring.
+ * Returns FLINTS_ENOMEM if they cannot be allocated.  Stream-ordered.
+ */
+int flints_synthesize(int64_t nside, int lmax, int spin, const void *alm, const void *blm, void *map,
+                      void *stream);
+
+/*
+ * Displaced pixel centres of the lensing remap (paper Sec. 3.1, vector form):
+ * n' = cos|d| n + sin|d| (d_theta e_theta + d_phi e_phi) / |d| at every RING pixel
+ * centre n of nside (n' = n where d = 0; no special case at the poles).
+ *   defl   device double[2][npix]: d_theta then d_phi (radians), as
+ *          flints_synthesize spin 1 writes it.
+ *   theta, phi  device double[npix]: colatitude in [0, pi], longitude in [0, 2 pi).
+ * Elementwise and stream-ordered; no workspace.
+ */
+int flints_lensed_directions(int64_t nside, const void *defl, void *theta, void *phi, void *stream);
+
 /* 1 if flints_interpolate_tqu shares the stencil search between these plans
  * (with_var_*: whether variances will be requested), 0 if it runs two
  * separate calls, < 0 on error.  Host-only; launches nothing. */

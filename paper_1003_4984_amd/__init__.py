@@ -5,7 +5,8 @@ this package only marshals arguments to it.  Importing the package does not load
 the library; the first call does, and raises if it has not been built.
 """
 from .flints import (  # noqa: F401
-    Plan, Batch, FlintsError, load_library, interpolate, interpolate_tqu, supersample, pixel_centres, tqu_shared, stencil, table_eval, BATCH_AUTOTUNE,
+    Plan, Batch, FlintsError, load_library, interpolate, interpolate_tqu, supersample, pixel_centres, tqu_shared,
+    stencil, table_eval, BATCH_AUTOTUNE, synthesize, lensed_directions, lens_tqu, alm_mmajor,
     FP64, FP32_IR, S2_FULL, S2_PAPER, NUG_ALWAYS, NUG_ON_FAILURE, VAR_PAPER, VAR_MSE,
     STENCIL_NEAREST, STENCIL_PIXEL, MAP_F64, MAP_F32,
 )

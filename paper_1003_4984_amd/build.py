@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libflints.so")
 # that the translation units compile in parallel.
 SOURCES = ["capi.hip", "tables.hip", "interp.hip", "interp_s0.hip", "interp_s2.hip", "interp_f32_s0.hip",
            "interp_f32_s2.hip", "interp_mse64_s0.hip", "interp_mse64_s2.hip", "interp_mse32_s0.hip",
-           "interp_mse32_s2.hip", "interp_tqu.hip", "supersample.hip", "fixed.hip", "batch.hip"]
+           "interp_mse32_s2.hip", "interp_tqu.hip", "supersample.hip", "fixed.hip", "batch.hip", "sht.hip"]
 ARCH = os.environ.get("FLINTS_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled: some of their forms have produced wrong

@@ -437,6 +437,7 @@ flints_batch_t flints_batch_create(const flints_job_t *jobs, int njobs, int flag
 }
 
 int flints_batch_run(flints_batch_t batch, void *stream) {
+  (void)hipGetLastError();   // errors of earlier calls are not this call's
   if (!batch) { set_error("batch is NULL"); return FLINTS_EINVAL; }
   Batch *b = reinterpret_cast<Batch *>(batch);
   if (b->exec) {
@@ -450,6 +451,7 @@ int flints_batch_run(flints_batch_t batch, void *stream) {
 }
 
 int flints_batch_capture(flints_batch_t batch, void *stream) {
+  (void)hipGetLastError();   // errors of earlier calls are not this call's
   if (!batch) { set_error("batch is NULL"); return FLINTS_EINVAL; }
   Batch *b = reinterpret_cast<Batch *>(batch);
   hipStream_t s = (hipStream_t)stream;

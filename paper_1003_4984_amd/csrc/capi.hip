@@ -13,6 +13,12 @@ namespace flints {
 static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+// Start of an entry point: clears this thread's message and any HIP error left
+// by earlier calls of the caller, so that launch checks see only this call's.
+static void begin_call() {
+  g_last_error.clear();
+  (void)hipGetLastError();
+}
 
 static bool finite_nonneg(const double *v, int n) {
   for (int i = 0; i < n; ++i)
@@ -49,7 +55,7 @@ flints_plan_t flints_plan(int64_t nside, int lmax, const double *cl, int K, int 
 
 flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, int spin,
                              const flints_opts *opts) {
-  g_last_error.clear();
+  begin_call();
   flints_opts o;
   flints_default_opts(&o);
   if (opts) o = *opts;
@@ -190,7 +196,7 @@ static Plan *as_plan(flints_plan_t h) { return reinterpret_cast<Plan *>(h); }
 
 int flints_interpolate(flints_plan_t plan, const void *map, const double *theta, const double *phi,
                        int64_t n, void *out, void *var, void *stream) {
-  g_last_error.clear();
+  begin_call();
   if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
   if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
   if (n == 0) return FLINTS_OK;
@@ -224,7 +230,7 @@ static int check_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *ma
 int flints_interpolate_tqu(flints_plan_t plan_t, flints_plan_t plan_qu, const void *map_t,
                            const void *map_qu, const double *theta, const double *phi, int64_t n,
                            void *out_t, void *var_t, void *out_qu, void *var_qu, void *stream) {
-  g_last_error.clear();
+  begin_call();
   const int rc = check_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, n, out_t, out_qu);
   if (rc != FLINTS_OK || n == 0) return rc;
   return launch_interpolate_tqu(as_plan(plan_t), as_plan(plan_qu), (const double *)map_t,
@@ -236,7 +242,7 @@ int flints_interpolate_tqu_noalloc(flints_plan_t plan_t, flints_plan_t plan_qu, 
                                    const void *map_qu, const double *theta, const double *phi,
                                    int64_t n, void *out_t, void *var_t, void *out_qu, void *var_qu,
                                    void *stream) {
-  g_last_error.clear();
+  begin_call();
   const int rc = check_tqu(plan_t, plan_qu, map_t, map_qu, theta, phi, n, out_t, out_qu);
   if (rc != FLINTS_OK || n == 0) return rc;
   return launch_interpolate_tqu_noalloc(as_plan(plan_t), as_plan(plan_qu), (const double *)map_t,
@@ -246,15 +252,35 @@ int flints_interpolate_tqu_noalloc(flints_plan_t plan_t, flints_plan_t plan_qu, 
 }
 
 int flints_pixel_centres(int64_t nside, double *theta, double *phi, void *stream) {
-  g_last_error.clear();
+  begin_call();
   if (nside < 1 || nside > 16384) { set_error("nside must be in [1, 16384]"); return FLINTS_EINVAL; }
   if (!theta || !phi) { set_error("theta and phi must be non-NULL"); return FLINTS_EINVAL; }
   return launch_pixel_centres(nside, theta, phi, (hipStream_t)stream);
 }
 
+int flints_synthesize(int64_t nside, int lmax, int spin, const void *alm, const void *blm, void *map,
+                      void *stream) {
+  begin_call();
+  if (nside < 1 || nside > 8192) { set_error("nside must be in [1, 8192]"); return FLINTS_EINVAL; }
+  if (lmax < 0 || lmax > 16384) { set_error("lmax must be in [0, 16384]"); return FLINTS_EINVAL; }
+  if (spin < 0 || spin > 2) { set_error("spin must be 0, 1 or 2"); return FLINTS_EINVAL; }
+  if (!alm || !map) { set_error("alm and map must be non-NULL"); return FLINTS_EINVAL; }
+  if (spin != 2 && blm) { set_error("blm is taken by spin-2 synthesis only (pass NULL)"); return FLINTS_EINVAL; }
+  return launch_synthesize(nside, lmax, spin, (const double *)alm, (const double *)blm, (double *)map,
+                           (hipStream_t)stream);
+}
+
+int flints_lensed_directions(int64_t nside, const void *defl, void *theta, void *phi, void *stream) {
+  begin_call();
+  if (nside < 1 || nside > 16384) { set_error("nside must be in [1, 16384]"); return FLINTS_EINVAL; }
+  if (!defl || !theta || !phi) { set_error("defl, theta and phi must be non-NULL"); return FLINTS_EINVAL; }
+  return launch_lensed_directions(nside, (const double *)defl, (double *)theta, (double *)phi,
+                                  (hipStream_t)stream);
+}
+
 int flints_supersample(flints_plan_t plan, const void *map, int64_t nside_out, void *out, void *var,
                        void *stream) {
-  g_last_error.clear();
+  begin_call();
   if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
   if (nside_out < 1 || nside_out > 16384) { set_error("nside_out must be in [1, 16384]"); return FLINTS_EINVAL; }
   if (!map || !out) { set_error("map and out must be non-NULL"); return FLINTS_EINVAL; }
@@ -263,7 +289,7 @@ int flints_supersample(flints_plan_t plan, const void *map, int64_t nside_out, v
 }
 
 int flints_tqu_shared(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_t, int with_var_qu) {
-  g_last_error.clear();
+  begin_call();
   if (!plan_t || !plan_qu) { set_error("plans must be non-NULL"); return FLINTS_EINVAL; }
   const double some = 0.0;   // stands for a variance array; only its presence matters
   return tqu_shareable(as_plan(plan_t), as_plan(plan_qu), with_var_t ? &some : nullptr,
@@ -272,7 +298,7 @@ int flints_tqu_shared(flints_plan_t plan_t, flints_plan_t plan_qu, int with_var_
 
 int flints_stencil(flints_plan_t plan, const double *theta, const double *phi, int64_t n,
                    int64_t *idx, void *stream) {
-  g_last_error.clear();
+  begin_call();
   if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
   if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
   if (n == 0) return FLINTS_OK;
@@ -281,7 +307,7 @@ int flints_stencil(flints_plan_t plan, const double *theta, const double *phi, i
 }
 
 int flints_table_eval(flints_plan_t plan, const double *s, int64_t n, double *out, void *stream) {
-  g_last_error.clear();
+  begin_call();
   if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
   if (n < 0) { set_error("n must be >= 0"); return FLINTS_EINVAL; }
   if (n == 0) return FLINTS_OK;
@@ -290,7 +316,7 @@ int flints_table_eval(flints_plan_t plan, const double *s, int64_t n, double *ou
 }
 
 int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info) {
-  g_last_error.clear();
+  begin_call();
   if (!plan || !info) { set_error("plan and info must be non-NULL"); return FLINTS_EINVAL; }
   const Plan *p = as_plan(plan);
   info->nside = p->d.nside;
@@ -319,7 +345,7 @@ int flints_plan_info(flints_plan_t plan, flints_plan_info_t *info) {
 }
 
 int flints_plan_stats(flints_plan_t plan, flints_stats *st, void *stream) {
-  g_last_error.clear();
+  begin_call();
   if (!plan || !st) { set_error("plan and stats must be non-NULL"); return FLINTS_EINVAL; }
   unsigned long long c[CNT_N];
   hipStream_t s = (hipStream_t)stream;
@@ -338,7 +364,7 @@ int flints_plan_stats(flints_plan_t plan, flints_stats *st, void *stream) {
 }
 
 int flints_plan_reset_stats(flints_plan_t plan, void *stream) {
-  g_last_error.clear();
+  begin_call();
   if (!plan) { set_error("plan is NULL"); return FLINTS_EINVAL; }
   if (hipMemsetAsync(as_plan(plan)->d_counters, 0, sizeof(unsigned long long) * CNT_N,
                      (hipStream_t)stream) != hipSuccess) {

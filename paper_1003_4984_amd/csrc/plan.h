@@ -88,6 +88,11 @@ hipMemPool_t workspace_pool();
 int launch_supersample(const Plan *p, const double *map, int64_t nside_out, double *out, double *var,
                        hipStream_t s);
 int launch_pixel_centres(int64_t nside, double *theta, double *phi, hipStream_t s);
+// Lensing pipeline (sht.hip): spin-s synthesis of a RING map from a_lm, and
+// the displaced pixel centres for a deflection map.
+int launch_synthesize(int64_t N, int lmax, int spin, const double *alm, const double *blm, double *map,
+                      hipStream_t s);
+int launch_lensed_directions(int64_t N, const double *defl, double *theta, double *phi, hipStream_t s);
 // Fixed-stencil tables (fixed.hip): classes, representative stencils and
 // factors; and the per-target and stencil launchers of that mode.
 int build_fixed(Plan *p);

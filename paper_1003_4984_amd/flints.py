@@ -68,7 +68,7 @@ BATCH_AUTOTUNE = 1
 
 EXPORTS = ["flints_default_opts", "flints_plan", "flints_plan_ex", "flints_interpolate",
            "flints_interpolate_tqu", "flints_interpolate_tqu_noalloc", "flints_tqu_shared",
-           "flints_supersample", "flints_pixel_centres",
+           "flints_supersample", "flints_pixel_centres", "flints_synthesize", "flints_lensed_directions",
            "flints_stencil", "flints_table_eval", "flints_plan_info", "flints_plan_stats",
            "flints_plan_reset_stats", "flints_plan_destroy", "flints_last_error",
            "flints_batch_create", "flints_batch_run", "flints_batch_capture", "flints_batch_info",
@@ -101,6 +101,10 @@ def load_library(path=LIB_PATH):
     lib.flints_pixel_centres.restype = c_int
     lib.flints_supersample.argtypes = [vp, dp, i64, dp, dp, vp]
     lib.flints_supersample.restype = c_int
+    lib.flints_synthesize.argtypes = [i64, c_int, c_int, dp, dp, dp, vp]
+    lib.flints_synthesize.restype = c_int
+    lib.flints_lensed_directions.argtypes = [i64, dp, dp, dp, vp]
+    lib.flints_lensed_directions.restype = c_int
     lib.flints_tqu_shared.argtypes = [vp, vp, c_int, c_int]
     lib.flints_tqu_shared.restype = c_int
     lib.flints_stencil.argtypes = [vp, dp, dp, i64, dp, vp]
@@ -320,6 +324,82 @@ def pixel_centres(nside, device="cuda", stream=None):
                                   _stream(stream))
     _check(lib, rc, "flints_pixel_centres")
     return th, ph
+
+
+def alm_mmajor(a):
+    """Host complex a[l, m] (m <= l, numpy) -> float64 array of the m-major
+    interleaved layout flints_synthesize takes ((l, m) at m(2 lmax+3-m)/2 + l-m)."""
+    import numpy as np
+    a = np.asarray(a)
+    lmax = a.shape[0] - 1
+    out = np.empty(((lmax + 1) * (lmax + 2) // 2, 2), dtype=np.float64)
+    pos = 0
+    for m in range(lmax + 1):
+        col = a[m:, m]
+        out[pos:pos + col.size, 0] = col.real
+        out[pos:pos + col.size, 1] = col.imag
+        pos += col.size
+    return out.reshape(-1)
+
+
+def synthesize(nside, lmax, spin, alm, blm=None, out=None, stream=None):
+    """Spin-s synthesis on the device (flints_synthesize): spin 0 alm = T_lm ->
+    T; spin 1 alm = phi_lm -> (d_theta, d_phi); spin 2 (alm, blm) = (E_lm, B_lm)
+    -> (Q, U).  alm/blm: device float64 tensors in the m-major interleaved
+    layout (alm_mmajor).  Returns the map tensor (planes of 12 nside^2)."""
+    import torch
+    lib = load_library()
+    nalm = 2 * (int(lmax) + 1) * (int(lmax) + 2) // 2
+    if alm.numel() != nalm or (blm is not None and blm.numel() != nalm):
+        raise FlintsError(f"alm/blm must hold {nalm} float64 values (lmax {lmax})")
+    npix = 12 * int(nside) * int(nside)
+    planes = 1 if spin == 0 else 2
+    if out is None:
+        out = torch.empty(planes * npix, dtype=torch.float64, device=alm.device)
+    if out.numel() != planes * npix:
+        raise FlintsError("out has the wrong size")
+    rc = lib.flints_synthesize(int(nside), int(lmax), int(spin), _ptr(alm, "alm", torch.float64),
+                               _ptr(blm, "blm", torch.float64), _ptr(out, "map", torch.float64),
+                               _stream(stream))
+    _check(lib, rc, "flints_synthesize")
+    return out
+
+
+def lensed_directions(nside, defl, theta=None, phi=None, stream=None):
+    """Displaced pixel centres (flints_lensed_directions) for a deflection map
+    defl = (d_theta, d_phi) planes.  Returns (theta', phi')."""
+    import torch
+    lib = load_library()
+    npix = 12 * int(nside) * int(nside)
+    if defl.numel() != 2 * npix:
+        raise FlintsError(f"defl must hold 2 x {npix} values")
+    if theta is None:
+        theta = torch.empty(npix, dtype=torch.float64, device=defl.device)
+    if phi is None:
+        phi = torch.empty(npix, dtype=torch.float64, device=defl.device)
+    rc = lib.flints_lensed_directions(int(nside), _ptr(defl, "defl", torch.float64),
+                                      _ptr(theta, "theta", torch.float64), _ptr(phi, "phi", torch.float64),
+                                      _stream(stream))
+    _check(lib, rc, "flints_lensed_directions")
+    return theta, phi
+
+
+def lens_tqu(plan_t, plan_qu, lmax, tlm, elm, blm, plm, want_var=True, stream=None):
+    """The lensing pipeline of paper Sec. 3.1 on the device: unlensed T and
+    (Q, U) maps and the deflection grad(phi) by synthesis, the displaced pixel
+    centres, and T+Q/U interpolation there.  Plans of one N_side (spin 0 and
+    spin 2); harmonic coefficients as device tensors in the m-major layout.
+    Returns (out_t, var_t, out_qu, var_qu, theta', phi')."""
+    nside = plan_t.nside
+    if plan_qu.nside != nside:
+        raise FlintsError("plans must share N_side")
+    t_map = synthesize(nside, lmax, 0, tlm, stream=stream)
+    qu_map = synthesize(nside, lmax, 2, elm, blm, stream=stream)
+    defl = synthesize(nside, lmax, 1, plm, stream=stream)
+    th, ph = lensed_directions(nside, defl, stream=stream)
+    del defl
+    res = interpolate_tqu(plan_t, plan_qu, t_map, qu_map, th, ph, want_var=want_var, stream=stream)
+    return (*res, th, ph)
 
 
 def tqu_shared(plan_t, plan_qu, with_var=True):

@@ -102,6 +102,7 @@ extern "C" __global__ void k_wigner_sums(const double *__restrict__ coef, int lm
 extern "C" int synth_wigner_sums(const double *coef, int lmax, int s, const double *theta, int R,
                                  double *A, double *B, void *stream) {
   if (R <= 0 || lmax < 0) return 0;
+  (void)hipGetLastError();   // an earlier call's error is not this launch's
   const int threads = 128;
   dim3 grid((R + threads - 1) / threads, lmax + 1, 1);
   hipLaunchKernelGGL(k_wigner_sums, grid, dim3(threads), 0, (hipStream_t)stream, coef, lmax, s,
