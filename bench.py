@@ -55,8 +55,9 @@ TRAFFIC_FILES = {
 
 
 # Sources outside the measured single-plan and T+Q/U kernels: the batched
-# launches.
-NOT_MEASURED = ("batch.hip",)
+# launches, the pixel-tied stencils, supersampling and the synthesis (each a
+# translation unit of its own that the measured kernels do not include).
+NOT_MEASURED = ("batch.hip", "fixed.hip", "supersample.hip", "sht.hip")
 
 
 def kernel_source_hash():

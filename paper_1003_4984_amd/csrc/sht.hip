@@ -29,7 +29,9 @@
 // Stockham passes when n is a power of two (the belt rings at power-of-two
 // N_side), otherwise Bluestein's chirp-z form q j = (q^2 + j^2 - (j - q)^2)/2, a
 // circular convolution of power-of-two length M >= 2n - 1.  Rings of equal
-// transform length are batched into one set of passes.
+// transform length are batched into one set of passes; the passes run in
+// global memory only until each row has split into independent transforms of
+// at most 2048 points, which then finish in LDS.
 #include "plan.h"
 #include "healpix_ring.h"
 #include <algorithm>
@@ -38,6 +40,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 namespace flints {
@@ -116,6 +119,13 @@ __device__ inline void step_d(double a, double cb, ScaledD &st) {
   }
 }
 
+// The same step for a lane whose scale is 2^0 (no rescaling can be due).
+__device__ inline void step_plain(double a, double cb, ScaledD &st) {
+  const double next = a * st.cur - cb * st.prev;
+  st.prev = st.cur;
+  st.cur = next;
+}
+
 // Stage 1.  X, Z: [ring 1..4N-1][m 0..lmax] (Z unused for spin 0).
 template <int S>
 __global__ __launch_bounds__(SHT_TPB) void k_sht_rings(int64_t N, int lmax, const double *__restrict__ elm,
@@ -173,28 +183,42 @@ __global__ __launch_bounds__(SHT_TPB) void k_sht_rings(int64_t N, int lmax, cons
     }
     __syncthreads();
     const int cnt = min(SHT_CH, lmax - lb + 1);
-    if (live) {
+    // Once every lane of the wave has left the scaled range (E = 0, 2^E = 1)
+    // the chunk runs the plain recurrence: no scale factor, no rescaling test.
+    const bool scaled = __any(live && (dp.E < 0 || (S != 0 && dm.E < 0)));
+    auto chunk = [&](auto checked) {
+      constexpr bool CHK = decltype(checked)::value;
       for (int t = 0; t < cnt; ++t) {
         const int l = lb + t;
         const cplx ap = sap[t];
-        const double vp = dp.cur * dp.sf;
+        const double vp = CHK ? dp.cur * dp.sf : dp.cur;
         if (S == 0) {
           if (l & 1) { s3.re += vp * ap.re; s3.im += vp * ap.im; }
           else       { s1.re += vp * ap.re; s1.im += vp * ap.im; }
-          step_d(sc1[t] * x, scb[t], dp);
+          if (CHK) step_d(sc1[t] * x, scb[t], dp);
+          else step_plain(sc1[t] * x, scb[t], dp);
         } else {
           const cplx am = sam[t];
-          const double vm = dm.cur * dm.sf;
+          const double vm = CHK ? dm.cur * dm.sf : dm.cur;
           const double pvp = (l & 1) ? -vp : vp, pvm = (l & 1) ? -vm : vm;
           s1.re += vm * ap.re;  s1.im += vm * ap.im;
           s2.re += vp * am.re;  s2.im += vp * am.im;
           s3.re += pvp * ap.re; s3.im += pvp * ap.im;
           s4.re += pvm * am.re; s4.im += pvm * am.im;
           const double c1x = sc1[t] * x, c0 = sc0[t], cb = scb[t];
-          step_d(c1x - c0, cb, dp);
-          step_d(c1x + c0, cb, dm);
+          if (CHK) {
+            step_d(c1x - c0, cb, dp);
+            step_d(c1x + c0, cb, dm);
+          } else {
+            step_plain(c1x - c0, cb, dp);
+            step_plain(c1x + c0, cb, dm);
+          }
         }
       }
+    };
+    if (live) {
+      if (scaled) chunk(std::true_type{});
+      else chunk(std::false_type{});
     }
   }
   if (!live) return;
@@ -311,6 +335,47 @@ __global__ void k_stockham(const cplx *__restrict__ in, cplx *__restrict__ out, 
     yr[k + 2 * j * m] = cadd(c0, c1);
     yr[k + 2 * j * m + m] = cmul(w, csub(c0, c1));
   }
+}
+
+// The remaining passes of a length-M transform once the Stockham stride has
+// reached m0 = M / MS: each residue class r mod m0 of a row is then an
+// independent length-MS transform (every butterfly of a pass with stride
+// m >= m0 joins elements of one class), so the block for (r, row) gathers
+// x[r + m0 t], t < MS, into LDS, runs the passes with strides 1 .. MS/2 there
+// (the same butterflies and twiddles W_M^{j m} as the global passes) and
+// writes the class back in place.
+constexpr int FFT_LDS_N = 2048;   // sub-transform length held in LDS (2 x 32 KB)
+constexpr int FFT_LDS_TPB = 256;
+
+// Blocks go to the 8 XCDs round robin, so block b is mapped to row 8 q' + b % 8
+// and residue q % m0 (q = b / 8, q' = q / m0): the m0 blocks of one row, which
+// read interleaved words of the same lines, run on one XCD and share its L2.
+__global__ __launch_bounds__(FFT_LDS_TPB) void k_fft_lds(cplx *__restrict__ data, int64_t rows, int M, int MS,
+                                                        int m0, const cplx *__restrict__ Wt, int inverse) {
+  extern __shared__ cplx sm[];
+  cplx *a = sm, *b = sm + MS;
+  const int64_t q = blockIdx.x / 8;
+  const int r = (int)(q % m0);
+  const int64_t rw = (q / m0) * 8 + blockIdx.x % 8;
+  if (rw >= rows) return;
+  cplx *row = data + rw * M + r;
+  for (int t = threadIdx.x; t < MS; t += blockDim.x) a[t] = row[(int64_t)m0 * t];
+  __syncthreads();
+  for (int l = MS / 2, mm = 1; l >= 1; l >>= 1, mm <<= 1) {
+    for (int i = threadIdx.x; i < MS / 2; i += blockDim.x) {
+      const int j = i / mm, k = i - j * mm;
+      const cplx c0 = a[k + j * mm], c1 = a[k + j * mm + l * mm];
+      cplx w = Wt[(int64_t)j * mm * m0];
+      if (inverse) w.im = -w.im;
+      b[k + 2 * j * mm] = cadd(c0, c1);
+      b[k + 2 * j * mm + mm] = cmul(w, csub(c0, c1));
+    }
+    __syncthreads();
+    cplx *t = a;
+    a = b;
+    b = t;
+  }
+  for (int t = threadIdx.x; t < MS; t += blockDim.x) row[(int64_t)m0 * t] = a[t];
 }
 
 // A[slot] *= B[its chirp spectrum].
@@ -475,6 +540,8 @@ static int ring_groups(int64_t N, std::vector<SynthGroup> &out) {
 
 int launch_synthesize(int64_t N, int lmax, int spin, const double *elm, const double *blm, double *map,
                       hipStream_t s) {
+  hipFuncSetAttribute((const void *)k_fft_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      2 * FFT_LDS_N * (int)sizeof(cplx));
   std::vector<SynthGroup> groups;
   const int rc = ring_groups(N, groups);
   if (rc != FLINTS_OK) return rc;
@@ -510,12 +577,17 @@ int launch_synthesize(int64_t N, int lmax, int spin, const double *elm, const do
     hipLaunchKernelGGL(k_roots, dim3(grid1d(M / 2, tb, 256)), dim3(tb), 0, s, M, Wt);
     if (spin == 0) hipLaunchKernelGGL(k_fold<0>, dim3(gx, nj), dim3(tb), 0, s, N, lmax, X, Z, g.djobs, nj, M, chirp, A);
     else hipLaunchKernelGGL(k_fold<1>, dim3(gx, nj), dim3(tb), 0, s, N, lmax, X, Z, g.djobs, nj, M, chirp, A);
+    // global radix-2 passes while the stride is below m0, then the rest in LDS
+    const int MS = std::min(M, FFT_LDS_N), m0 = M / MS;
     auto fft = [&](cplx *&src, cplx *&dst, int64_t rows, int inverse) {
       const unsigned blocks = grid1d(rows * (M / 2), tb, 65536);
-      for (int l = M / 2, m = 1; l >= 1; l >>= 1, m <<= 1) {
+      for (int l = M / 2, m = 1; m < m0; l >>= 1, m <<= 1) {
         hipLaunchKernelGGL(k_stockham, dim3(blocks), dim3(tb), 0, s, src, dst, rows, M, l, m, Wt, inverse);
         std::swap(src, dst);
       }
+      const int64_t nblk = ((rows + 7) / 8) * 8 * m0;
+      hipLaunchKernelGGL(k_fft_lds, dim3((unsigned)nblk), dim3(FFT_LDS_TPB), 2 * MS * sizeof(cplx), s, src, rows,
+                         M, MS, m0, Wt, inverse);
     };
     cplx *a = A, *a2 = A2;
     if (chirp) {
