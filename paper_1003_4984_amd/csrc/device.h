@@ -52,7 +52,7 @@ constexpr int WAVE = 64;
 constexpr int MAX_WPB = 8;      // waves per block of the interpolation kernels (launch bound 512)
 constexpr int STENCIL_WPB = 4;  // waves per block of the stencil kernel (launch bound 256)
 constexpr int CAND_CAP = 320;
-constexpr int NBF = 10;  // doubles per neighbour record
+constexpr int NBF = 8;   // doubles per neighbour record
 constexpr double PI_D = 3.14159265358979323846;
 constexpr double TWO_PI_D = 6.28318530717958647692;
 
@@ -157,7 +157,7 @@ inline Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int
   L.off_mat = a;   a = al16(a + nsys * L.matsz * 8);
   L.off_rhs = a;   a = al16(a + nsys * n * NR * 8);
   L.off_col = a;
-  L.off_rbuf = a;  a = al16(a + nsys * 4 * 8);
+  L.off_rbuf = a;
   L.wave_bytes = s > a ? s : a;
   return L;
 }
@@ -334,7 +334,9 @@ __device__ bool knn_search(const PlanDev &P, double th, double ph, int lane, dou
 // nb_stride(K)) so that lanes reading the records of consecutive neighbours
 // read consecutive words.  Record 0 is the target.  Fields: chord offset from
 // the target in the target's (e_theta, e_phi, z) frame (0-2), the point's own
-// e_theta (3-5) and e_phi (6-7) in that frame, gathered map values (8-9).
+// e_theta (3-5) and e_phi (6-7) in that frame.  The gathered map values go
+// straight to the data column of the right-hand sides (column NR - 1 of the
+// neighbour's rows).
 
 // Map value i (float32 maps are widened exactly); zero without a map.
 __device__ __forceinline__ double map_value(const PlanDev &P, const double *__restrict__ map, int64_t i) {
@@ -342,9 +344,9 @@ __device__ __forceinline__ double map_value(const PlanDev &P, const double *__re
   return P.map_f32 ? (double)((const float *)map)[i] : map[i];
 }
 
-template <int SPIN>
+template <int SPIN, int NR>
 __device__ void neighbour_records(const PlanDev &P, double th, double ph, int lane, const int *sel,
-                                  double *nb, const double *__restrict__ map) {
+                                  double *nb, double *rhs, const double *__restrict__ map) {
   double zt, st;
   sincos_bounded(th, st, zt);
   const double twopi = kconst(TWO_PI_D);
@@ -357,7 +359,6 @@ __device__ void neighbour_records(const PlanDev &P, double th, double ph, int la
       f[0] = 0.0; f[1] = 0.0; f[2] = 0.0;
       f[3] = zt;  f[4] = 0.0; f[5] = -st;
       f[6] = 0.0; f[7] = 1.0;
-      f[8] = 0.0; f[9] = 0.0;
     } else {
       const int64_t p = sel[a - 1];
       const Ring R = ring_geom(P.nside, pix_ring(P.nside, p));
@@ -371,8 +372,13 @@ __device__ void neighbour_records(const PlanDev &P, double th, double ph, int la
       f[2] = R.z - zt;
       f[3] = R.z * cd; f[4] = R.z * sd; f[5] = -R.s;
       f[6] = -sd;      f[7] = cd;
-      f[8] = map_value(P, map, p);                     // no map: the conditioning probe
-      f[9] = (SPIN == 2) ? map_value(P, map, P.npix + p) : 0.0;
+      // data column of the neighbour's rows (no map: the conditioning probe)
+      if (SPIN == 0) {
+        rhs[(a - 1) * NR + NR - 1] = map_value(P, map, p);
+      } else {
+        rhs[2 * (a - 1) * NR + NR - 1] = map_value(P, map, p);
+        rhs[(2 * (a - 1) + 1) * NR + NR - 1] = map_value(P, map, P.npix + p);
+      }
     }
 #pragma unroll
     for (int i = 0; i < NBF; ++i) nb[i * ns + a] = f[i];
@@ -449,7 +455,6 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
       const int ra = a - 1;
       mat[tri(ra) + ra] = 1.0;
       rhs[ra * NR + 0] = c[0];
-      rhs[ra * NR + 1] = nb[8 * ns + a];
     } else {
       const int ra = 2 * (a - 1);
       mat[tri(ra) + ra] = 1.0;
@@ -459,8 +464,6 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
       rhs[ra * NR + 1] = c[1];          // Cov(Q_a, U_0)
       rhs[(ra + 1) * NR + 0] = c[2];    // Cov(U_a, Q_0)
       rhs[(ra + 1) * NR + 1] = c[3];    // Cov(U_a, U_0)
-      rhs[ra * NR + 2] = nb[8 * ns + a];
-      rhs[(ra + 1) * NR + 2] = nb[9 * ns + a];
     }
   }
   // off-diagonal pair q = (a - 1)(a - 2) / 2 + (b - 1), 0 <= q < K (K - 1) / 2,
@@ -639,7 +642,7 @@ template <int SPIN, int NR>
 __device__ inline void phase_a_build(const PlanDev &P, const double *tab,
                                      const double *__restrict__ map, double th, double ph, int lane,
                                      const int *sel, double *nb, double *mat, double *rhs) {
-  neighbour_records<SPIN>(P, th, ph, lane, sel, nb, map);
+  neighbour_records<SPIN, NR>(P, th, ph, lane, sel, nb, rhs, map);
   assemble<SPIN, NR>(P, tab, nb, lane, mat, rhs);
 }
 
@@ -666,6 +669,12 @@ __device__ inline const double *load_table(char *lds, const PlanDev &P) {
   for (int i = threadIdx.x; i < ntabd; i += blockDim.x) ((double *)lds)[i] = P.tab[i];
   __syncthreads();
   return (const double *)lds;
+}
+
+// The correlation table a kernel reads: its LDS copy, or (layouts with no table
+// bytes) the plan's table in device memory, read through the caches.
+__device__ inline const double *kernel_table(char *lds, const PlanDev &P, const Layout &L) {
+  return L.tab_bytes ? load_table(lds, P) : P.tab;
 }
 
 template <int G>

@@ -81,7 +81,11 @@ static int launch_tqu_t(const Plan *p0, const Plan *p2, const double *map0, cons
   constexpr int PPW2 = T2 ? 1 : 4;
   const DevLimits lim = device_limits();
   const int K = p0->d.K;
-  const Layout L2 = make_layout(p2->d.ntab, p2->d.nfun, K, p2->d.n, PPW2, 1, 3, SCR);
+  Layout L2 = make_layout(p2->d.ntab, p2->d.nfun, K, p2->d.n, PPW2, 1, 3, SCR);
+  // The tile pass reads the correlation table through the caches instead of
+  // an LDS copy: the 64-row systems then fit eight waves per CU (20,480 B of
+  // LDS each at K = 32) instead of seven.
+  if (T2) L2.tab_bytes = 0;
   const Layout L0 = make_layout(p0->d.ntab, p0->d.nfun, K, p0->d.n, 4, 1, 2);
   auto k2 = [] {
     if constexpr (T2 != 0) return k_interp_tile_st<T2>;
