@@ -21,6 +21,9 @@ def main():
     ap.add_argument("--scale", type=float, default=0.25, help="scale of the target counts")
     ap.add_argument("--jobs", type=int, default=64)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32ir"],
+                    help="plan precision; FP32+IR plans whose creation probe keeps FP32 run outside "
+                         "the persistent launches")
     args = ap.parse_args()
     import torch
     import paper_1003_4984_amd as fl
@@ -45,7 +48,8 @@ def main():
         key = (nside, lmax, K, spin)
         if key not in plans:
             cl = tt if spin == 0 else np.concatenate([ee, bb])
-            plans[key] = fl.Plan(nside, lmax, cl, K, spin)
+            plans[key] = fl.Plan(nside, lmax, cl, K, spin,
+                                 precision=fl.FP64 if args.precision == "fp64" else fl.FP32_IR)
         th, ph = configs.uniform_targets(4, sp["job"], sp["n"], "cuda")
         nf = 1 if spin == 0 else 2
         out = torch.empty(nf * sp["n"], dtype=torch.float64, device="cuda")
@@ -102,7 +106,9 @@ def main():
         "points": int(points), "samples": int(samples), "scale": args.scale,
         "sequential_samples_per_s": samples / t_seq, "batch_samples_per_s": samples / t_batch,
         "graph_samples_per_s": samples / t_graph, "autotuned_samples_per_s": samples / t_auto,
-        "autotune_s": t_tune, "setup_s": t_setup,
+        "autotune_s": t_tune, "setup_s": t_setup, "precision": args.precision,
+        "plans_running_fp32": sum(1 for p in plans.values() if p.info()["precision"] == fl.FP32_IR),
+        "plans": len(plans),
         "bit_identical": {"batch": ok_batch, "graph": ok_graph, "autotuned": ok_auto},
         "batch_info": info_plain, "autotuned_info": info_auto,
     }

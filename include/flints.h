@@ -383,9 +383,13 @@ typedef struct {
   int fused_jobs;            /* jobs on the persistent launches */
   int classes;               /* persistent launch groups used per run */
   /* per launch group g = 6 * engine + bucket: engine by rows n <= 16, 32, 48,
-   * 64; bucket by correlation-table size <= 16, 36, 57, 77, 98 KB, larger */
+   * 64; bucket (row-group engines only; the tile engines, n > 32, read their
+   * tables through the caches and use bucket 0) by correlation-table size
+   * <= 16, 36, 57, 77, 98 KB, larger */
   int tiles[24];
-  int tile_points[24];       /* targets per tile (0 = group unused) */
+  int tile_points[24];       /* targets per tile (0 = group unused); a tile is
+                                taken by one block (row-group engines) or one
+                                wave (tile engines) */
   int waves_per_block[24];
   int captured;              /* 1 if runs replay a graph */
 } flints_batch_info_t;

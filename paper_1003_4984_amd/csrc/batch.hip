@@ -3,10 +3,12 @@
 // Jobs are grouped by system-size class (row group n <= 16 / n <= 32, tile
 // n <= 48 / n <= 64) and cut into tiles of consecutive targets (multiples of 64
 // so fix-up chunks never straddle tiles).  One persistent launch per class:
-// every block takes the next tile from a device queue (an atomic counter),
-// reloads the job's correlation table into LDS when the job changes, and runs
-// the shared per-group / per-point bodies of device.h, so a target gets exactly
-// the arithmetic of flints_interpolate.  Spin 0 and spin 2 jobs share a launch
+// in the row-group classes every block takes the next tile from a device queue
+// (an atomic counter) and reloads the job's correlation table into LDS when the
+// job changes; in the tile classes, whose systems fill the LDS, the tables are
+// read through the caches and every wave takes tiles on its own.  Both run the
+// shared per-group / per-point bodies of device.h, so a target gets exactly the
+// arithmetic of flints_interpolate.  Spin 0 and spin 2 jobs share a launch
 // (both bodies are compiled into it).  A second persistent launch per class
 // runs the fix-up pass over the same tiles.  The queue counters are cleared by
 // a kernel at the start of every run, which keeps the sequence capturable in a
@@ -75,6 +77,9 @@ __device__ inline void batch_tile_fixup(const BatchJob &J, const double *tab, co
 }
 
 // Persistent launch over the class's tile queue (FIX selects the fix-up pass).
+// Tile classes read their tables through the caches, so each wave takes tiles
+// on its own (no block barriers); row-group classes copy the job's table to
+// LDS, so a block takes a tile and shares it among its waves.
 template <int CLS, bool FIX>
 __global__ __launch_bounds__(MAX_WPB * WAVE) void k_batch(const BatchJob *__restrict__ jobs,
                                                const BatchTile *__restrict__ tiles, int ntiles,
@@ -86,7 +91,25 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_batch(const BatchJob *__rest
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, wave);
-  const double *tab = (const double *)lds;
+  if constexpr (CLS >= 2) {
+    for (;;) {
+      int t = 0;
+      if (lane == 0) t = (int)atomicAdd(ctr, 1u);
+      t = __shfl(t, 0);
+      if (t >= ntiles) break;
+      const BatchTile T = tiles[t];
+      const BatchJob &J = jobs[T.job];
+      if (J.P.spin == 0) {
+        if (FIX) batch_tile_fixup<CLS, 0>(J, J.P.tab, B, T, 0, 1, lane);
+        else batch_tile_main<CLS, 0>(J, J.P.tab, B, T, 0, 1, lane);
+      } else {
+        if (FIX) batch_tile_fixup<CLS, 2>(J, J.P.tab, B, T, 0, 1, lane);
+        else batch_tile_main<CLS, 2>(J, J.P.tab, B, T, 0, 1, lane);
+      }
+    }
+    return;
+  }
+  const bool lds_tab = L.tab_bytes != 0;   // table copied to LDS, or read through the caches
   int cur = -1;
   for (;;) {
     if (threadIdx.x == 0) s_tile = (int)atomicAdd(ctr, 1u);
@@ -96,12 +119,13 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_batch(const BatchJob *__rest
     if (t >= ntiles) break;
     const BatchTile T = tiles[t];
     const BatchJob &J = jobs[T.job];
-    if (T.job != cur) {
+    if (lds_tab && T.job != cur) {
       const int nt = J.P.ntab * J.P.nfun;
       for (int i = threadIdx.x; i < nt; i += blockDim.x) ((double *)lds)[i] = J.P.tab[i];
       __syncthreads();
       cur = T.job;
     }
+    const double *tab = lds_tab ? (const double *)lds : J.P.tab;
     if (J.P.spin == 0) {
       if (FIX) batch_tile_fixup<CLS, 0>(J, tab, B, T, wave, wpb, lane);
       else batch_tile_main<CLS, 0>(J, tab, B, T, wave, wpb, lane);
@@ -118,7 +142,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_batch(const BatchJob *__rest
 struct ClassRun {
   int used = 0;
   int max_K = 0, max_n = 0, max_tab = 0;
-  int tile_pts = 4096;
+  int tile_pts = 4096;   // targets per tile (tile classes: per wave, set at creation)
   int wpb = 0, occ = 1, lds = 0;
   Layout L{};
   BatchTile *d_tiles = nullptr;
@@ -137,17 +161,17 @@ struct Batch {
   int64_t points = 0;
 };
 
-// Launch group of a job: engine by system size, and table-size bucket, so a
-// large table (few waves fit beside it in LDS) does not set the occupancy of
-// jobs with small ones.  The bucket edges are where the 64-row tile engine
-// (21,056 B of LDS per wave) loses a wave per CU: 7, 6, 5, 4 and 3 waves fit
-// beside tables of at most 16, 36, 57, 77 and 98 KB.
+// Launch group of a job: engine by system size, and for the row-group engines
+// (which copy the table to LDS) a table-size bucket, so that a large table does
+// not set the occupancy of jobs with small ones.  The tile engines read the
+// table through the caches, so each is one launch group whatever the tables.
 static int job_class(const Plan *p) {
   if (p->d.precision != FLINTS_FP64 || p->d.var_kind != FLINTS_VAR_PAPER) return -1;
   if (p->d.stencil_mode != FLINTS_STENCIL_NEAREST) return -1;   // tabulated stencils: own kernel
   const int n = p->d.n;
   if (n > 64) return -1;   // the multi-pass engine runs through the single-plan path
   const int e = n <= 16 ? 0 : n <= 32 ? 1 : n <= 48 ? 2 : 3;
+  if (e >= 2) return NTABB * e;
   const int tb = p->d.ntab * p->d.nfun * 8;
   static const int edge_kb[NTABB - 1] = {16, 36, 57, 77, 98};
   int k = 0;
@@ -218,6 +242,9 @@ static int size_class(ClassRun &r, int c, int wpb_cap) {
   const int ppw = e < 2 ? 4 : 1;
   const int min_mat = e < 2 ? 0 : e * TILE_D + 16;   // tile path T = e + 1: T - 1 staged tiles + pivots
   r.L = make_layout(r.max_tab, 1, r.max_K, r.max_n, ppw, 1, 3, min_mat);
+  // tile classes read the job's table through the caches: their systems fill
+  // the LDS, and a table copy beside them would cost waves
+  if (e >= 2) r.L.tab_bytes = 0;
   int lds_max = 0, ncu = 0, dev = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
@@ -323,8 +350,12 @@ static double time_candidate(Batch *b, int c, int tile_pts, int wpb_cap, int64_t
 
 // Autotuner: tile sizes x waves-per-block caps, timed on the first
 // `sample` targets of every job of the class; the fastest is kept.
+constexpr int WAVE_TILE_PTS = 128;   // default tile of the tile classes (taken by one wave)
+
 static void autotune(Batch *b, int c) {
-  static const int tiles[] = {256, 1024, 4096, 16384};
+  static const int block_tiles[] = {256, 1024, 4096, 16384};
+  static const int wave_tiles[] = {64, 128, 256, 1024};
+  const int *tiles = c / NTABB >= 2 ? wave_tiles : block_tiles;
   static const int caps[] = {MAX_WPB, 4, 2};
   int64_t cls_pts = 0, njobs = 0;
   for (size_t j = 0; j < b->jobs.size(); ++j)
@@ -332,8 +363,9 @@ static void autotune(Batch *b, int c) {
   const int64_t sample = std::max<int64_t>(16384, (1 << 18) / std::max<int64_t>(njobs, 1));
   double best = 1e30;
   int bt = b->run[c].tile_pts, bw = MAX_WPB;
-  for (int tp : tiles)
+  for (int ti = 0; ti < 4; ++ti)
     for (int cap : caps) {
+      const int tp = tiles[ti];
       const double t = time_candidate(b, c, tp, cap, sample);
       if (t < best) { best = t; bt = tp; bw = cap; }
     }
@@ -413,6 +445,7 @@ flints_batch_t flints_batch_create(const flints_job_t *jobs, int njobs, int flag
   for (int c = 0; c < NCLASS; ++c) {
     ClassRun &r = b->run[c];
     if (!r.used) continue;
+    if (c / NTABB >= 2) r.tile_pts = WAVE_TILE_PTS;
     if (size_class(r, c, MAX_WPB) != FLINTS_OK) { free_batch(b); return nullptr; }
     if (flags & FLINTS_BATCH_AUTOTUNE) autotune(b, c);
     std::vector<BatchTile> t = make_tiles(*b, c, r.tile_pts, -1);

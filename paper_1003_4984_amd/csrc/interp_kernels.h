@@ -436,7 +436,12 @@ inline int launch_tile(const Plan *p, const double *map, const double *theta, co
     return launch_pair(k_interp64<16 * T, G, SPIN, false, true>, k_fixup<TileEngine<T, SPIN>, SPIN>, p,
                        L, PPW, map, theta, phi, n, out, var, s);
   }
-  const Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 1, 1, NR, SCR);
+  Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 1, 1, NR, SCR);
+  // the table is read through the caches when its LDS copy would cost waves
+  const DevLimits lim = device_limits();
+  if (lim.lds_max / L.wave_bytes > (lim.lds_max - L.tab_bytes) / L.wave_bytes &&
+      (lim.lds_max - L.tab_bytes) / L.wave_bytes < MAX_WPB)
+    L.tab_bytes = 0;
   return launch_pair(k_interp_tile<T, SPIN>, k_fixup<TileEngine<T, SPIN>, SPIN>, p, L, 1, map, theta,
                      phi, n, out, var, s);
 }

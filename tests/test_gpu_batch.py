@@ -116,7 +116,9 @@ def test_batch_autotune(gpu_ok):
     info = b.info()
     for c in range(len(info["tiles"])):
         if info["tiles"][c]:
-            assert info["tile_points"][c] in (256, 1024, 4096, 16384)
+            # launch groups 12.. are the tile engines, whose waves take tiles one by one
+            sizes = (64, 128, 256, 1024) if c >= 12 else (256, 1024, 4096, 16384)
+            assert info["tile_points"][c] in sizes
             assert 1 <= info["waves_per_block"][c] <= 8
     for *_, out, var in jobs:
         out.fill_(0.0)
