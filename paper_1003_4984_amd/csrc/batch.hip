@@ -109,7 +109,6 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_batch(const BatchJob *__rest
     }
     return;
   }
-  const bool lds_tab = L.tab_bytes != 0;   // table copied to LDS, or read through the caches
   int cur = -1;
   for (;;) {
     if (threadIdx.x == 0) s_tile = (int)atomicAdd(ctr, 1u);
@@ -119,13 +118,13 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_batch(const BatchJob *__rest
     if (t >= ntiles) break;
     const BatchTile T = tiles[t];
     const BatchJob &J = jobs[T.job];
-    if (lds_tab && T.job != cur) {
+    if (T.job != cur) {
       const int nt = J.P.ntab * J.P.nfun;
       for (int i = threadIdx.x; i < nt; i += blockDim.x) ((double *)lds)[i] = J.P.tab[i];
       __syncthreads();
       cur = T.job;
     }
-    const double *tab = lds_tab ? (const double *)lds : J.P.tab;
+    const double *tab = (const double *)lds;
     if (J.P.spin == 0) {
       if (FIX) batch_tile_fixup<CLS, 0>(J, tab, B, T, wave, wpb, lane);
       else batch_tile_main<CLS, 0>(J, tab, B, T, wave, wpb, lane);

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_fixed_build(PlanDev P, int64
   constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
-  const double *tab = kernel_table(lds, P, Lay);
+  const double *tab = load_table(lds, P);
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp64(PlanDev P, const do
   constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
-  const double *tab = kernel_table(lds, P, L);
+  const double *tab = load_table(lds, P);
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_escalate(PlanDev P, const do
   constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
-  const double *tab = kernel_table(lds, P, L);
+  const double *tab = load_table(lds, P);
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs(PlanDev P, const d
                                                    double *__restrict__ var, Layout L) {
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
-  const double *tab = kernel_table(lds, P, L);
+  const double *tab = load_table(lds, P);
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs_st(
     Layout L, int *__restrict__ stn, int64_t s0, int64_t s1) {
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
-  const double *tab = kernel_table(lds, P, L);
+  const double *tab = load_table(lds, P);
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_rs_ld(
     Layout L, const int *__restrict__ stn, int64_t s0, int64_t s1) {
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
-  const double *tab = kernel_table(lds, P, L);
+  const double *tab = load_table(lds, P);
   const int wpb = blockDim.x / WAVE;
   const int wave = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
