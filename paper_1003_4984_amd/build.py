@@ -31,13 +31,22 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False, jobs=None):
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the same
+# sources (device code is compiled as usual; every -fsanitize is host-only).
+# Loaded by tests/test_host_sanitizers.py with the clang ASan runtime preloaded.
+HOSTSAN_LIB = os.path.join(HERE, "libflints_hostsan.so")
+HOSTSAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                 "-Xarch_host", "-shared-libsan"]
+
+
+def build(verbose=False, jobs=None, out_path=LIB, extra=(), tag=""):
     cc = hipcc()
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, "_obj_" + src.replace(".hip", ".o"))
-        cmd = [cc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(CSRC, "_obj_" + tag + src.replace(".hip", ".o"))
+        cmd = [cc, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -53,19 +62,38 @@ def build(verbose=False, jobs=None):
     if failed:
         msg = "\n".join(f"--- {s}\n{t}" for s, t in failed)
         raise RuntimeError("hipcc failed:\n" + msg)
-    tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    tmp = out_path + ".tmp"
+    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *extra, *objs, "-o", tmp]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))
-    os.replace(tmp, LIB)
+    os.replace(tmp, out_path)
     for o in objs:
         try:
             os.remove(o)
         except OSError:
             pass
-    return LIB
+    return out_path
+
+
+def build_hostsan(verbose=False):
+    """libflints_hostsan.so: the library with host-side ASan + UBSan."""
+    return build(verbose, out_path=HOSTSAN_LIB, extra=HOSTSAN_FLAGS, tag="san_")
+
+
+def asan_runtime():
+    """The clang ASan runtime matching hipcc (to preload for the sanitized library)."""
+    import glob
+    root = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    cands = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                          "libclang_rt.asan-x86_64.so")) +
+                   glob.glob(os.path.join(root, "lib", "llvm", "lib", "clang", "*", "lib", "linux",
+                                          "libclang_rt.asan-x86_64.so")))
+    return cands[-1] if cands else None
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--hostsan" in sys.argv:
+        print(build_hostsan(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
