@@ -123,8 +123,10 @@ void flints_default_opts(flints_opts *o);
  *          correlation_func sums from l = 1).  spin 2: C^EE_l for l = 0..lmax
  *          followed by C^BB_l for l = 0..lmax (l < 2 ignored).  Must be finite
  *          and non-negative; read during the call only.
- *   K      stencil size, 1 <= K <= min(64, 12 nside^2) for spin 0 and
- *          1 <= K <= 32 for spin 2 (a 2K x 2K system of at most 64 rows).
+ *   K      stencil size, 1 <= K <= min(64, 12 nside^2) (spin 2: a real 2K x 2K
+ *          system).  Spin-2 plans with K > 32 (64 < 2K <= 128 rows) run an
+ *          FP64 elimination in LDS: FLINTS_FP32_IR runs them in FP64, and
+ *          FLINTS_VAR_MSE is refused for them (NULL).
  *   spin   0 (temperature) or 2 (Q, U polarisation).
  * The correlation function is built on the current HIP device in FP64 and kept
  * in device memory.  Returns NULL on error (see flints_last_error()).
@@ -339,8 +341,8 @@ void flints_plan_destroy(flints_plan_t plan);
  * correlation table into LDS when the job changes, and run the same per-point
  * arithmetic as flints_interpolate (results are bit-identical to it); spin 0
  * and spin 2 jobs mix freely within a class.  Jobs with FP32_IR or MSE-variance
- * plans, and jobs whose system has more than 64 rows (spin 2 with K > 32), run
- * through the single-plan path in the same stream.  Batching is an
+ * plans, and jobs whose system has more than 64 rows (spin 2 with K > 32, the LDS
+ * elimination), run through the single-plan path in the same stream.  Batching is an
  * addition to the method: the paper interpolates one map at a time.
  */
 typedef struct {

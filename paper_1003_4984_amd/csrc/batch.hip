@@ -168,7 +168,7 @@ static int job_class(const Plan *p) {
   if (p->d.precision != FLINTS_FP64 || p->d.var_kind != FLINTS_VAR_PAPER) return -1;
   if (p->d.stencil_mode != FLINTS_STENCIL_NEAREST) return -1;   // tabulated stencils: own kernel
   const int n = p->d.n;
-  if (n > 64) return -1;   // the multi-pass engine runs through the single-plan path
+  if (n > 64) return -1;   // the LDS elimination runs through the single-plan path
   const int e = n <= 16 ? 0 : n <= 32 ? 1 : n <= 48 ? 2 : 3;
   if (e >= 2) return NTABB * e;
   const int tb = p->d.ntab * p->d.nfun * 8;

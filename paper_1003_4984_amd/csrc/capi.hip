@@ -72,18 +72,17 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
     set_error("K must be in [1, min(64, npix)]");
     return nullptr;
   }
-  if (spin == 2 && K > 32) {
-    // the multi-pass engine for systems above 64 rows is switched off: it made
-    // a GPU memory fault whose cause is not found yet
-    set_error("spin-2 plans support K <= 32 (systems of at most 64 rows)");
-    return nullptr;
-  }
   if (o.precision != FLINTS_FP64 && o.precision != FLINTS_FP32_IR) { set_error("bad precision"); return nullptr; }
   if (o.spin2_mode != FLINTS_S2_FULL && o.spin2_mode != FLINTS_S2_PAPER) { set_error("bad spin2_mode"); return nullptr; }
   if (o.nugget != FLINTS_NUG_ALWAYS && o.nugget != FLINTS_NUG_ON_FAILURE) { set_error("bad nugget policy"); return nullptr; }
   if (o.var_kind != FLINTS_VAR_PAPER && o.var_kind != FLINTS_VAR_MSE) { set_error("bad var_kind"); return nullptr; }
   if (o.stencil != FLINTS_STENCIL_NEAREST && o.stencil != FLINTS_STENCIL_PIXEL) { set_error("bad stencil"); return nullptr; }
   if (o.map_type != FLINTS_MAP_F64 && o.map_type != FLINTS_MAP_F32) { set_error("bad map_type"); return nullptr; }
+  if (spin == 2 && K > 32 && o.stencil == FLINTS_STENCIL_NEAREST && o.var_kind == FLINTS_VAR_MSE) {
+    // systems above 64 rows run the LDS elimination, which forms the paper variance only
+    set_error("FLINTS_VAR_MSE supports systems of at most 64 rows (spin 2: K <= 32)");
+    return nullptr;
+  }
   if (o.stencil == FLINTS_STENCIL_PIXEL) {
     if ((spin == 0 && K > 48) || (spin == 2 && K > 16)) {
       set_error("FLINTS_STENCIL_PIXEL supports at most 48 rows (spin 0: K <= 48, spin 2: K <= 16)");
@@ -138,6 +137,7 @@ flints_plan_t flints_plan_ex(int64_t nside, int lmax, const double *cl, int K, i
   d.var_kind = o.var_kind;
   d.precision = o.precision;
   d.n = spin == 0 ? K : 2 * K;
+  if (d.n > 64) d.precision = FLINTS_FP64;   // the elimination above 64 rows is FP64 only
   d.eps = 1.4901161193847656e-08;  // 2^-26 = sqrt(double epsilon), paper Sec. 2.4
   d.sigma2 = spin == 0 ? s0 : 0.5 * s0;
   d.pivot_ratio_min = o.pivot_ratio_min > 0.0 ? o.pivot_ratio_min : 1e-3;

@@ -1476,6 +1476,96 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
   }
 }
 
+// ---------------------------------------------------------------- phase B, 64 < n <= 128
+// Systems above 64 rows (spin 2 with 32 < K <= 64): S + nI = L D L^T (unit lower
+// L, D the pivots) by right-looking elimination in the wave's packed system in
+// LDS.  At step k the trailing triangle a_ij -= a_ik a_jk / d_k (i >= j > k) is
+// cut into 8 x 8 tiles, one entry per lane; column tiles run in the outer loop,
+// so a lane reads its multiplier a_jk / d_k once per column tile.  Every lane is
+// busy except in the diagonal tiles' upper halves.  The right-hand sides ride
+// along (r_i -= a_ik r_k / d_k), so row k of them is final at step k: with
+// z = L^-1 b, b^T (S + nI)^-1 b = sum_k z_k^2 / d_k, and value and quad
+// accumulate as the row-group and tile engines form them.  Every lane ends with
+// the same sums.  mat holds tri(n) + WAVE doubles: the last WAVE take the stores
+// of masked-off lanes, so the stores need no branch.  Returns false if a pivot
+// is not positive.
+constexpr int LDS_TB = 4;   // row tiles whose loads are issued together
+
+template <int SPIN, int NR>
+__device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow, double nug, GroupOut &o) {
+  bool ok = true;
+  double v0 = 0.0, v1 = 0.0, q0 = 0.0, q1 = 0.0;
+  const int dummy = tri(nrow) + lane;
+  const int tr = lane >> 3, tc = lane & 7;   // entry of an 8 x 8 tile
+#pragma unroll 1
+  for (int k = 0; k < nrow; ++k) {
+    compiler_fence();   // step k reads what step k - 1 wrote from other lanes
+    const double dk = mat[tri(k) + k] + nug;
+    ok = ok && (dk > 0.0);
+    const double ik = recip(dk);
+    double rk[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) rk[q] = rhs[k * NR + q];
+    if (SPIN == 0) {
+      v0 = fma(rk[0] * rk[1], ik, v0);
+      q0 = fma(rk[0] * rk[0], ik, q0);
+    } else {
+      v0 = fma(rk[0] * rk[NR - 1], ik, v0);
+      v1 = fma(rk[1] * rk[NR - 1], ik, v1);
+      q0 = fma(rk[0] * rk[0], ik, q0);
+      q1 = fma(rk[1] * rk[1], ik, q1);
+    }
+    // right-hand-side rows i > k
+#pragma unroll 1
+    for (int i = k + 1 + lane; i < nrow; i += WAVE) {
+      const double g = mat[tri(i) + k] * ik;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) rhs[i * NR + q] = fma(-g, rk[q], rhs[i * NR + q]);
+    }
+    // trailing triangle in 8 x 8 tiles (column k is not written in this step;
+    // loads of clamped indices stay inside the system: tri(i) + j < tri(n) for
+    // i, j < n)
+    const int m0 = k + 1;
+    const int nt = (nrow - m0 + 7) >> 3;
+    const int tlast = tri(nrow - 1);
+#pragma unroll 1
+    for (int J = 0; J < nt; ++J) {
+      const int j = m0 + 8 * J + tc;
+      const bool jv = j < nrow;
+      const int jc = jv ? j : nrow - 1;
+      const double fj = mat[tri(jc) + k] * ik;
+      // row tiles in groups of LDS_TB: every load of a group is issued before
+      // its stores; rows past the system read row n - 1 and store to the dummy
+#pragma unroll 1
+      for (int I0 = J; I0 < nt; I0 += LDS_TB) {
+        const int ib = m0 + 8 * I0 + tr;
+        const int tb = tri(ib);
+        double a[LDS_TB], x[LDS_TB];
+        int wi[LDS_TB];
+#pragma unroll
+        for (int u = 0; u < LDS_TB; ++u) {
+          const int i = ib + 8 * u;
+          const bool iv = i < nrow;
+          const int ti = iv ? tb + 8 * u * ib + 4 * u * (8 * u + 1) : tlast;
+          a[u] = mat[ti + k];
+          x[u] = mat[ti + jc];
+          wi[u] = (iv && jv && j <= i) ? ti + jc : dummy;
+        }
+        compiler_fence();
+#pragma unroll
+        for (int u = 0; u < LDS_TB; ++u) mat[wi[u]] = fma(-a[u], fj, x[u]);
+      }
+    }
+  }
+  compiler_fence();
+  o.v0 = v0;
+  o.v1 = v1;
+  o.qd0 = q0;
+  o.qd1 = q1;
+  o.w0 = o.w1 = 0.0;
+  return ok;
+}
+
 // Phase-B engines of the fix-up pass: solve the tagged point (searched and
 // assembled into the wave's first system buffer) with nugget nug, using
 // exactly the arithmetic of the matching main pass.  `first` is false when an
@@ -1501,6 +1591,18 @@ struct TileEngine {
     if (!found) return true;
     if (!first) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
     return __all(tile_phase_any<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o));
+  }
+};
+
+template <int SPIN>
+struct LdsEngine {
+  static constexpr int NR = (SPIN == 0) ? 2 : 3;
+  __device__ static bool solve(const PlanDev &P, const double *tab, const double *map, double th,
+                               double ph, int lane, const WaveBufs &B, bool found, bool first,
+                               double nug, GroupOut &o) {
+    if (!found) return true;
+    if (!first) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
+    return lds_phase_b<SPIN, NR>(B.mat, B.rhs, lane, P.n, nug, o);
   }
 };
 
@@ -1588,6 +1690,25 @@ __device__ inline void point_tile(const PlanDev &P, const double *tab, const dou
   const double th = theta[pt], ph = phi[pt];
   const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
   tile_solve<T, SPIN>(P, tab, map, th, ph, n, out, var, B, B.sel, pt, found, lane);
+}
+
+// One point on the whole wave with the LDS elimination (64 < n <= 128).
+template <int SPIN>
+__device__ inline void point_lds(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                                 const double *__restrict__ theta, const double *__restrict__ phi,
+                                 int64_t n, double *__restrict__ out, double *__restrict__ var,
+                                 const WaveBufs &B, int64_t pt, int lane) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  const double th = theta[pt], ph = phi[pt];
+  const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
+  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+  GroupOut o;
+  bool ok = true;
+  if (found) {
+    phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
+    ok = lds_phase_b<SPIN, NR>(B.mat, B.rhs, lane, P.n, nug, o);
+  }
+  if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
 }
 
 // ---------------------------------------------------------------- shared stencils (T + Q/U)

@@ -208,6 +208,27 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
     point_tile<T, SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
 }
 
+// Main pass for 64 < n <= 128 (spin 2 with 32 < K <= 64): one point per wave,
+// LDS elimination.  The packed systems (up to 66 KB per wave) leave no room for
+// an LDS copy of the table, which is read through the caches (layouts with no
+// table bytes).
+template <int SPIN>
+__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_lds(PlanDev P, const double *__restrict__ map,
+                                                    const double *__restrict__ theta,
+                                                    const double *__restrict__ phi, int64_t n,
+                                                    double *__restrict__ out,
+                                                    double *__restrict__ var, Layout L) {
+  extern __shared__ double lds_dyn[];
+  char *lds = (char *)lds_dyn;
+  const double *tab = kernel_table(lds, P, L);
+  const int wpb = blockDim.x / WAVE;
+  const int wave = threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  const WaveBufs B = wave_bufs(lds, L, wave);
+  for (int64_t pt = xcd_block() * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb)
+    point_lds<SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
+}
+
 // Main pass and fix-up pass for 64 < n <= 16 T (T = 6, 8; spin 2 with K > 32):
 // one point per wave with the multi-pass tile engine.  The trailing tiles need
 // the whole register file of a SIMD, so a block holds one wave per SIMD; the
@@ -458,15 +479,36 @@ inline int launch_tile_big(const Plan *p, const double *map, const double *theta
                      theta, phi, n, out, var, s);
 }
 
+// LDS elimination for 64 < n <= 128 (FP64, paper variance).
+template <int SPIN>
+inline int launch_lds(const Plan *p, const double *map, const double *theta, const double *phi,
+                      int64_t n, double *out, double *var, hipStream_t s) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
+  // the packed system plus WAVE doubles that absorb the masked-off stores
+  Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 1, 1, NR, tri(p->d.n) + WAVE);
+  L.tab_bytes = 0;   // the table is read through the caches; LDS holds the systems
+  return launch_pair(k_interp_lds<SPIN>, k_fixup<LdsEngine<SPIN>, SPIN>, p, L, 1, map, theta, phi, n, out,
+                     var, s);
+}
+
 template <int SPIN, bool MSE, bool FP32>
 inline int launch_spin(const Plan *p, const double *map, const double *theta, const double *phi,
                        int64_t n, double *out, double *var, hipStream_t s) {
   const int nrow = p->d.n;
-  if (nrow > 64) {
-    // plan creation refuses systems of more than 64 rows: the multi-pass tile
-    // engine for them (launch_tile_big) is switched off
-    set_error("systems of more than 64 rows are not supported");
+  if (nrow > 128) {
+    set_error("systems of more than 128 rows are not supported");
     return FLINTS_ELIMIT;
+  }
+  if (nrow > 64) {
+    // the LDS elimination (FP64, paper variance); plan creation refuses the MSE
+    // variance above 64 rows and runs FP32 plans of this size in FP64.  (The
+    // multi-pass tile engine, launch_tile_big, is switched off.)
+    if constexpr (MSE || FP32) {
+      set_error("systems of more than 64 rows run in FP64 with the paper variance only");
+      return FLINTS_ELIMIT;
+    } else {
+      return launch_lds<SPIN>(p, map, theta, phi, n, out, var, s);
+    }
   }
   if (!MSE && nrow <= 16) return launch_rs<1, SPIN, FP32>(p, map, theta, phi, n, out, var, s);
   if (!MSE && nrow <= 32) return launch_rs<2, SPIN, FP32>(p, map, theta, phi, n, out, var, s);

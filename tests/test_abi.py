@@ -46,8 +46,11 @@ def test_default_opts_and_error_paths():
     ptr2 = cl2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert not lib.flints_plan(8, 10, ptr2, 65, 2)                 # K <= 64
     assert b"K" in lib.flints_last_error()
-    assert not lib.flints_plan(8, 10, ptr2, 33, 2)                 # spin 2: K <= 32
-    assert b"K <= 32" in lib.flints_last_error()
+    o3 = flints._Opts()
+    lib.flints_default_opts(ctypes.byref(o3))
+    o3.var_kind = flints.VAR_MSE                                   # MSE variance: <= 64 rows
+    assert not lib.flints_plan_ex(8, 10, ptr2, 33, 2, ctypes.byref(o3))
+    assert b"FLINTS_VAR_MSE" in lib.flints_last_error()
     assert not lib.flints_plan(1, 10, ptr, 13, 0)                  # K <= npix = 12
     assert b"K" in lib.flints_last_error()
     o2 = flints._Opts()

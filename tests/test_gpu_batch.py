@@ -15,7 +15,8 @@ from _gpu_helpers import dev, gpu_stencil, reconcile_stencils, compare
 pytestmark = pytest.mark.gpu
 
 # (nside, K, spin, precision, var_kind, points): classes n <= 16, 32, 48, 64 for
-# both spins, plus FP32 and MSE jobs on the single-plan path and an empty job
+# both spins, plus FP32, MSE and 80-row (spin-2 K 40) jobs on the single-plan
+# path and an empty job
 JOBS = [
     (32, 12, 0, fl.FP64, fl.VAR_PAPER, 9000),
     (64, 16, 2, fl.FP64, fl.VAR_PAPER, 20000),
@@ -27,6 +28,7 @@ JOBS = [
     (64, 64, 0, fl.FP64, fl.VAR_PAPER, 3000),
     (32, 16, 0, fl.FP32_IR, fl.VAR_PAPER, 4000),
     (32, 16, 2, fl.FP64, fl.VAR_MSE, 4000),
+    (32, 40, 2, fl.FP64, fl.VAR_PAPER, 1500),
     (16, 16, 0, fl.FP64, fl.VAR_PAPER, 0),
 ]
 
@@ -76,7 +78,8 @@ def test_batch_equals_single(gpu_ok):
     info = b.info()
     assert info["njobs"] == len(JOBS) and info["classes"] >= 4
     assert all((t > 0) == (w > 0) for t, w in zip(info["tiles"], info["waves_per_block"]))
-    assert info["fused_jobs"] == sum(1 for j in JOBS if j[3] == fl.FP64 and j[4] == fl.VAR_PAPER and j[5] > 0)
+    assert info["fused_jobs"] == sum(1 for j in JOBS if j[3] == fl.FP64 and j[4] == fl.VAR_PAPER and j[5] > 0
+                                     and (j[1] if j[2] == 0 else 2 * j[1]) <= 64)
     b.run()
     torch.cuda.synchronize()
     _check_equal(jobs, ref)

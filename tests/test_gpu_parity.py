@@ -96,18 +96,11 @@ def test_parity_cfg1(cfg1):
     assert st["bad_inputs"] == 0 and st["search_failures"] == 0 and st["table_range"] == 0
 
 
-MULTIPASS_OFF = ("the multi-pass tile engine for systems above 64 rows is switched off: it made a GPU "
-                 "memory fault (four waves per block) whose cause is not found; spin-2 plans refuse K > 32")
-
-
 @pytest.mark.parametrize("mode", [fl.S2_FULL, fl.S2_PAPER])
-@pytest.mark.parametrize("K", [8, 16, 24, 32,
-                               pytest.param(40, marks=pytest.mark.skip(reason=MULTIPASS_OFF)),
-                               pytest.param(48, marks=pytest.mark.skip(reason=MULTIPASS_OFF)),
-                               pytest.param(64, marks=pytest.mark.skip(reason=MULTIPASS_OFF))])
+@pytest.mark.parametrize("K", [8, 16, 24, 32, 40, 48, 64])
 def test_parity_spin2(gpu_ok, mode, K):
     """K <= 32: row groups and the 64-row tile engine; K = 40, 48 (80, 96 rows)
-    and 64 (128 rows) would run the multi-pass tile engine, switched off."""
+    and 64 (128 rows): the LDS elimination."""
     nside, lmax = 64, 160
     tt, ee, te, bb = spectra.cl_acoustic(lmax)
     bb = 0.1 * ee

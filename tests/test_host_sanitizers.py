@@ -41,7 +41,6 @@ DRIVER = textwrap.dedent(r'''
         (lambda: lib.flints_plan(64, 128, cl, 65, 0), "K"),
         (lambda: lib.flints_plan(64, 128, cl, 16, 1), "spin"),
         (lambda: lib.flints_plan(64, 128, bad_cl, 16, 0), ""),
-        (lambda: lib.flints_plan(64, 128, cl, 40, 2), "K"),
     ]
     for fn, word in cases:
         h = fn()
@@ -53,6 +52,9 @@ DRIVER = textwrap.dedent(r'''
     assert not lib.flints_plan_ex(64, 128, cl, 16, 0, c.byref(o2)) and err()
     o2 = F._Opts(); lib.flints_default_opts(c.byref(o2)); o2.map_type = 9
     assert not lib.flints_plan_ex(64, 128, cl, 16, 0, c.byref(o2)) and err()
+    cl2 = (c.c_double * 258)(*([0.0, 0.0] + [1.0 / (l * (l + 1)) for l in range(2, 129)]) * 2)
+    o2 = F._Opts(); lib.flints_default_opts(c.byref(o2)); o2.var_kind = F.VAR_MSE
+    assert not lib.flints_plan_ex(64, 128, cl2, 40, 2, c.byref(o2)) and "VAR_MSE" in err()
     # a valid plan: on a host without a GPU it fails at its first device call
     h = lib.flints_plan(64, 128, cl, 16, 0)
     if h:
