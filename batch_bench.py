@@ -2,8 +2,9 @@
 
 Jobs follow the batched configuration of the workload module (N_side in
 {128 .. 2048}, spin 0 or 2, K in {16, 24, 32, 48}, target counts log-uniform in
-[1e4, 5e7] times --scale, uniform random directions); spin-2 jobs drawn with
-K = 48 (96 rows, beyond the 64-row engines) use K = 32.  One map per
+[1e4, 5e7] times --scale, uniform random directions); spin-2 jobs with K = 48
+(96-row systems) run the LDS elimination through the single-plan path inside
+the batch.  One map per
 (N_side, spin) is shared by the jobs that use it.  Reports samples/s for the
 jobs run one after another through flints_interpolate, for one batched run, for
 graph replays and for an autotuned batch, and checks that all four agree bit
@@ -11,9 +12,14 @@ for bit.  Prints one JSON line.
 """
 import argparse
 import json
+import sys
 import time
 
 import numpy as np
+
+
+def log(msg):
+    print(f"[batch_bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -35,8 +41,6 @@ def main():
     maps, plans, jobs = {}, {}, []
     for sp in specs:
         nside, spin, K, lmax = sp["nside"], sp["spin"], sp["K"], sp["lmax"]
-        if spin == 2 and K > 32:
-            K = 32
         tt, ee, te, bb = spectra.cl_acoustic(lmax)
         if (nside, spin) not in maps:
             r = seeded(4, nside, spin)
@@ -60,28 +64,31 @@ def main():
     samples = sum(j[4].numel() for j in jobs)
     points = sum(j[2].numel() for j in jobs)
 
-    def timed(fn):
+    log(f"set up {len(jobs)} jobs, {points} targets in {t_setup:.1f} s")
+
+    def timed(fn, name):
         best = 1e30
-        for _ in range(args.reps):
+        for r in range(args.reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             fn()
             torch.cuda.synchronize()
             best = min(best, time.perf_counter() - t0)
+            log(f"{name} run {r + 1}/{args.reps}: {time.perf_counter() - t0:.2f} s")
         return best
 
     def sequential():
         for p, m, th, ph, out, var in jobs:
             fl.interpolate(p, m, th, ph, out=out, var=var)
 
-    t_seq = timed(sequential)
+    t_seq = timed(sequential, "per-job launches")
     ref = [(j[4].clone(), j[5].clone()) for j in jobs]
 
     def same():
         return all(torch.equal(j[4], r[0]) and torch.equal(j[5], r[1]) for j, r in zip(jobs, ref))
 
     b = fl.Batch(jobs)
-    t_batch = timed(b.run)
+    t_batch = timed(b.run, "batch")
     ok_batch = same()
     s = torch.cuda.Stream()
     b.capture(s)
@@ -90,14 +97,16 @@ def main():
         b.run(s)
         s.synchronize()
 
-    t_graph = timed(replay)
+    t_graph = timed(replay, "graph replay")
     ok_graph = same()
     info_plain = b.info()
     b.close()
+    log("autotuning")
     t0 = time.perf_counter()
     bt = fl.Batch(jobs, autotune=True)
     t_tune = time.perf_counter() - t0
-    t_auto = timed(bt.run)
+    log(f"autotuned in {t_tune:.1f} s")
+    t_auto = timed(bt.run, "autotuned batch")
     ok_auto = same()
     info_auto = bt.info()
     bt.close()

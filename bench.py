@@ -409,6 +409,44 @@ def leg_pixel_stencils(fl, torch, inp_main, pool):
     return res
 
 
+def leg_large_systems(fl, torch, inp_main, pool, stride=48):
+    """K 48 at the headline's N_side 4096, lmax 4096 maps, on every 48th target
+    of the headline workload: spin 0 (48-row systems, tile engine) and spin 2
+    (96-row systems, the LDS elimination), with a sampled parity check against
+    the oracle."""
+    from workload import configs
+    nside, K = 4096, 48
+    tt, ee, bb = inp_main["tt"], inp_main["ee"], inp_main["bb"]
+    lmax = len(tt) - 1
+    th = inp_main["theta"][::stride].contiguous()
+    ph = inp_main["phi"][::stride].contiguous()
+    n = th.numel()
+    p0 = fl.Plan(nside, lmax, tt, K, 0)
+    p2 = fl.Plan(nside, lmax, np.concatenate([ee, bb]), K, 2)
+    o0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    v0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    o2 = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    v2 = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    t0 = _time_calls(torch, lambda: fl.interpolate(p0, inp_main["T"], th, ph, out=o0, var=v0), steps=2)
+    t2 = _time_calls(torch, lambda: fl.interpolate(p2, inp_main["QU"], th, ph, out=o2, var=v2), steps=2)
+    r = {"workload": f"N_side {nside} lmax {lmax} K {K}, every {stride}th headline target",
+         "targets": n,
+         "T": {"rows": K, "engine": "tile", "samples_per_s": n / t0, "s": t0},
+         "QU": {"rows": 2 * K, "engine": "LDS elimination", "samples_per_s": 2.0 * n / t2, "s": t2},
+         "stats": {"T": p0.stats(), "QU": p2.stats()}}
+    if pool is not None:
+        sel = configs.parity_subset(3, n, 200, job=5)
+        sel_t = torch.as_tensor(sel, device="cuda")
+        ths, phs = th[sel_t].contiguous(), ph[sel_t].contiguous()
+        st = fl.stencil(p0, ths, phs).cpu().numpy()
+        g2 = torch.stack([o2[sel_t], o2[sel_t + n]], 1).cpu().numpy()
+        gv2 = torch.stack([v2[sel_t], v2[sel_t + n]], 1).cpu().numpy()
+        r["parity_sample"] = _oracle_parity_on(pool, nside, K, tt, (ee, bb), inp_main, ths.cpu().numpy(),
+                                               phs.cpu().numpy(), st, o0[sel_t].cpu().numpy(),
+                                               v0[sel_t].cpu().numpy(), g2, gv2)
+    return r
+
+
 _LENS_ALM = None
 
 
@@ -609,6 +647,7 @@ def run_legs(fl, torch, inp_main, pool, nw):
     for name, fn in (("nside512_fp64_vs_fp32ir", lambda: leg_nside512(fl, torch, pool, nw)),
                      ("supersample_2048_to_4096", lambda: leg_supersample(fl, torch)),
                      ("pixel_stencils", lambda: leg_pixel_stencils(fl, torch, inp_main, pool)),
+                     ("large_systems_K48", lambda: leg_large_systems(fl, torch, inp_main, pool)),
                      ("lensing_pipeline", lambda: leg_lensing_pipeline(fl, torch, inp_main, pool)),
                      ("serving_cfg5", lambda: leg_serving(fl, torch, inp_main))):
         log(f"leg {name}")

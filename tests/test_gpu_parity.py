@@ -191,6 +191,27 @@ def test_nugget_escalation_on_failure(gpu_ok):
     compare(v, var, vo, varo, 1e-6, 0.0, 2e-7 * s2)
 
 
+def test_nugget_escalation_on_failure_spin2_lds(gpu_ok):
+    """The same policy for an 80-row system (spin-2 K 40, the LDS elimination):
+    a single-l E spectrum gives (Q, U) at most 2(2l+1) = 14 modes, so S is
+    singular and the fix-up pass escalates the nugget with the LDS engine."""
+    nside, K, L = 16, 40, 3
+    ee = np.zeros(L + 1)
+    ee[L] = 1.0
+    bb = np.zeros(L + 1)
+    q, u = synth.synth(-synth.draw_alm(seeds.rng(8, 0, 0), ee, L), 2, nside)
+    q, u = q.numpy(), u.numpy()
+    p = fl.Plan(nside, L, np.concatenate([ee, bb]), K, 2, nugget=fl.NUG_ON_FAILURE)
+    rng = np.random.default_rng(8)
+    th, ph = np.arccos(rng.uniform(-1, 1, 128)), rng.uniform(0, 6.28, 128)
+    v, var = run_gpu(p, (q, u), th, ph)
+    assert p.stats()["nugget_escalations"] > 0
+    g = gpu_stencil(p, th, ph)
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, (ee, bb), K, 2, (q, u), th, ph, g, nugget="on_failure")
+    s2 = p.info()["sigma2"]
+    compare(v, var, vo, varo, 1e-6, 0.0, 2e-7 * s2)
+
+
 @pytest.mark.parametrize("spin", [0, 2])
 def test_var_mse(gpu_ok, spin):
     nside, lmax, K = 32, 80, 16
