@@ -1480,23 +1480,23 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
 // Systems above 64 rows (spin 2 with 32 < K <= 64): S + nI = L D L^T (unit lower
 // L, D the pivots) by right-looking elimination in the wave's packed system in
 // LDS.  At step k the trailing triangle a_ij -= a_ik a_jk / d_k (i >= j > k) is
-// cut into 8 x 8 tiles, one entry per lane; column tiles run in the outer loop,
-// so a lane reads its multiplier a_jk / d_k once per column tile.  Every lane is
-// busy except in the diagonal tiles' upper halves.  The right-hand sides ride
+// cut into 16 x 16 tiles, a 2 x 2 block of entries per lane; column tiles run in
+// the outer loop, so a lane reads its two multipliers a_jk / d_k once per column
+// tile.  Every lane is busy except in the diagonal tiles' upper halves.  The right-hand sides ride
 // along (r_i -= a_ik r_k / d_k), so row k of them is final at step k: with
 // z = L^-1 b, b^T (S + nI)^-1 b = sum_k z_k^2 / d_k, and value and quad
 // accumulate as the row-group and tile engines form them.  Every lane ends with
 // the same sums.  mat holds tri(n) + WAVE doubles: the last WAVE take the stores
 // of masked-off lanes, so the stores need no branch.  Returns false if a pivot
 // is not positive.
-constexpr int LDS_TB = 4;   // row tiles whose loads are issued together
+constexpr int LDS_TB = 2;   // row tiles whose loads are issued together
 
 template <int SPIN, int NR>
 __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow, double nug, GroupOut &o) {
   bool ok = true;
   double v0 = 0.0, v1 = 0.0, q0 = 0.0, q1 = 0.0;
   const int dummy = tri(nrow) + lane;
-  const int tr = lane >> 3, tc = lane & 7;   // entry of an 8 x 8 tile
+  const int tr = lane >> 3, tc = lane & 7;   // tile rows tr, tr + 8; columns tc, tc + 8
 #pragma unroll 1
   for (int k = 0; k < nrow; ++k) {
     compiler_fence();   // step k reads what step k - 1 wrote from other lanes
@@ -1522,38 +1522,55 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
 #pragma unroll
       for (int q = 0; q < NR; ++q) rhs[i * NR + q] = fma(-g, rk[q], rhs[i * NR + q]);
     }
-    // trailing triangle in 8 x 8 tiles (column k is not written in this step;
-    // loads of clamped indices stay inside the system: tri(i) + j < tri(n) for
-    // i, j < n)
+    // trailing triangle in 16 x 16 tiles, a 2 x 2 block of entries per lane
+    // (tile rows tr, tr + 8 and columns tc, tc + 8).  Column k is not written in
+    // this step; loads of clamped indices stay inside the system: tri(i) + j <
+    // tri(n) for i, j < n.
     const int m0 = k + 1;
-    const int nt = (nrow - m0 + 7) >> 3;
+    const int nt = (nrow - m0 + 15) >> 4;
     const int tlast = tri(nrow - 1);
 #pragma unroll 1
     for (int J = 0; J < nt; ++J) {
-      const int j = m0 + 8 * J + tc;
-      const bool jv = j < nrow;
-      const int jc = jv ? j : nrow - 1;
-      const double fj = mat[tri(jc) + k] * ik;
+      int jc[2];
+      bool jv[2];
+      double fj[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int j = m0 + 16 * J + tc + 8 * c;
+        jv[c] = j < nrow;
+        jc[c] = jv[c] ? j : nrow - 1;
+        fj[c] = mat[tri(jc[c]) + k] * ik;
+      }
       // row tiles in groups of LDS_TB: every load of a group is issued before
       // its stores; rows past the system read row n - 1 and store to the dummy
 #pragma unroll 1
       for (int I0 = J; I0 < nt; I0 += LDS_TB) {
-        const int ib = m0 + 8 * I0 + tr;
+        const int ib = m0 + 16 * I0 + tr;
         const int tb = tri(ib);
-        double a[LDS_TB], x[LDS_TB];
-        int wi[LDS_TB];
+        double a[LDS_TB][2], x[LDS_TB][2][2];
+        int wi[LDS_TB][2][2];
 #pragma unroll
-        for (int u = 0; u < LDS_TB; ++u) {
-          const int i = ib + 8 * u;
-          const bool iv = i < nrow;
-          const int ti = iv ? tb + 8 * u * ib + 4 * u * (8 * u + 1) : tlast;
-          a[u] = mat[ti + k];
-          x[u] = mat[ti + jc];
-          wi[u] = (iv && jv && j <= i) ? ti + jc : dummy;
-        }
+        for (int u = 0; u < LDS_TB; ++u)
+#pragma unroll
+          for (int rr = 0; rr < 2; ++rr) {
+            const int d = 16 * u + 8 * rr;
+            const int i = ib + d;
+            const bool iv = i < nrow;
+            const int ti = iv ? tb + d * ib + d * (d + 1) / 2 : tlast;
+            a[u][rr] = mat[ti + k];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              x[u][rr][c] = mat[ti + jc[c]];
+              wi[u][rr][c] = (iv && jv[c] && jc[c] <= i) ? ti + jc[c] : dummy;
+            }
+          }
         compiler_fence();
 #pragma unroll
-        for (int u = 0; u < LDS_TB; ++u) mat[wi[u]] = fma(-a[u], fj, x[u]);
+        for (int u = 0; u < LDS_TB; ++u)
+#pragma unroll
+          for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) mat[wi[u][rr][c]] = fma(-a[u][rr], fj[c], x[u][rr][c]);
       }
     }
   }
