@@ -400,11 +400,28 @@ __device__ __forceinline__ double recip(double d) {
 // <P_a P_b> = xi- e^{2i(psi_ab + psi_ba)}, the bearings psi taken from the chord
 // projected on each point's (e_theta, e_phi).  Returns false if the distance is
 // beyond the table.
+// sqrt(x) for x >= 0 by the reciprocal-square-root estimate and the same
+// Goldschmidt refinement steps as the correctly rounded routine, without its
+// rescaling of arguments below 2^-767 (squared chords between pixel centres and
+// targets are far above that); sqrt(0) = 0.
+__device__ __forceinline__ double sqrt_nonneg(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r, h = 0.5 * r;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+}
+
 template <int SPIN>
 __device__ __forceinline__ bool pair_cov(const PlanDev &P, const double *tab, const double *nb, int ns,
                                          int a, int b, bool paper, double (&c)[4]) {
   const double dx = nb[a] - nb[b], dy = nb[ns + a] - nb[ns + b], dz = nb[2 * ns + a] - nb[2 * ns + b];
-  const double s = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+  const double s = 0.5 * sqrt_nonneg(dx * dx + dy * dy + dz * dz);
   if (SPIN == 0) {
     double f;
     const bool in = table_lookup(tab, P.ntab, 1, P.inv_h, s, &f);
@@ -472,10 +489,12 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
   const int npairs = K * (K - 1) / 2;
 #pragma unroll 1
   for (int q = lane; q < npairs; q += WAVE) {
-    int m = (int)(0.5f * (1.0f + sqrtf(1.0f + 8.0f * (float)q)));   // m = a - 1
-    m -= (m * (m - 1) / 2 > q);
-    m += ((m + 1) * m / 2 <= q);
-    const int a = m + 1, b = q - m * (m - 1) / 2 + 1;
+    // m = a - 1 from the hardware square root (within an ulp), then made exact
+    const unsigned uq = (unsigned)q;
+    unsigned m = (unsigned)(0.5f * (1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)q)));
+    m -= (m * (m - 1u) / 2u > uq);
+    m += ((m + 1u) * m / 2u <= uq);
+    const int a = (int)m + 1, b = (int)(uq - m * (m - 1u) / 2u) + 1;
     double c[4];
     range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, b, paper, c);
     if (SPIN == 0) {
