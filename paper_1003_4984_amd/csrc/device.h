@@ -1805,23 +1805,30 @@ __device__ inline void group_rs_ld(const PlanDev &P, const double *tab, const do
                                    int64_t s0) {
   constexpr int PPW = 4;
   const int K = P.K;
+  // the group's directions and stencils, each read in one round trip: the
+  // stencils of p0 .. p0 + 3 are contiguous (no group of four crosses a chunk)
+  const int64_t pend = min(n, p0 + PPW);
+  const int64_t pl = p0 + (lane & (PPW - 1));
+  const bool lv = lane < PPW && pl < pend;
+  const double thl = lv ? theta[pl] : 0.0, phl = lv ? phi[pl] : 0.0;
+  const int nst = (int)(pend - p0) * K;
+  const int *src = stn + (p0 - s0) * K;
+  for (int e = lane; e < nst; e += WAVE) B.sel[e] = src[e];
   unsigned act_mask = 0;
 #pragma unroll 1
   for (int q = 0; q < PPW; ++q) {
     const int64_t pt = p0 + q;
     if (pt >= n) break;
-    const double th = theta[pt], ph = phi[pt];
+    const double th = readlane_d(thl, q), ph = readlane_d(phl, q);
     const bool good = (th >= 0.0) && (th <= kconst(PI_D)) && isfinite(ph);
     if (!good) {
       if (lane == 0) atomicAdd(P.counters + CNT_BAD_INPUT, 1ull);
       continue;
     }
-    const int *src = stn + (pt - s0) * K;
-    if (src[0] < 0) {
+    if (B.sel[q * K] < 0) {
       if (lane == 0) atomicAdd(P.counters + CNT_SEARCH_FAIL, 1ull);
       continue;
     }
-    for (int k = lane; k < K; k += WAVE) B.sel[q * K + k] = src[k];
     act_mask |= 1u << q;
   }
   group_rs_solve<NT, SPIN>(P, tab, map, theta, phi, n, out, var, B, B.sel, p0, lane, act_mask);
