@@ -458,14 +458,16 @@ __device__ __forceinline__ bool pair_cov(const PlanDev &P, const double *tab, co
 // LDS.  First pass: one neighbour per lane, its target covariances, data and
 // diagonal; second pass: the off-diagonal pairs (a, b), 1 <= b < a <= K, with no
 // per-pair branches.
+// w, nw: this wave's share when nw waves assemble one system together (the
+// loops stride over nw * WAVE lanes); one wave by default.
 template <int SPIN, int NR>
 __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, int lane,
-                         double *mat, double *rhs) {
+                         double *mat, double *rhs, int w = 0, int nw = 1) {
   const int K = P.K;
   const int ns = nb_stride(K);
   const bool paper = (P.mode == FLINTS_S2_PAPER);
   bool range_bad = false;
-  for (int a = 1 + lane; a <= K; a += WAVE) {
+  for (int a = 1 + lane + w * WAVE; a <= K; a += nw * WAVE) {
     double c[4];
     range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, 0, paper, c);
     if (SPIN == 0) {
@@ -488,7 +490,7 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
   // fixed trip count
   const int npairs = K * (K - 1) / 2;
 #pragma unroll 1
-  for (int q = lane; q < npairs; q += WAVE) {
+  for (int q = lane + w * WAVE; q < npairs; q += nw * WAVE) {
     // m = a - 1 from the hardware square root (within an ulp), then made exact
     const unsigned uq = (unsigned)q;
     unsigned m = (unsigned)(0.5f * (1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)q)));
@@ -1510,8 +1512,13 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
 // is not positive.
 constexpr int LDS_TB = 2;   // row tiles whose loads are issued together
 
+// With nw > 1 waves of one block on the system (w = this wave), the right-hand-
+// side rows and the tile groups of each step are dealt round robin and a block
+// barrier ends every step; every wave must call it, the assembled system
+// visible to all of them.
 template <int SPIN, int NR>
-__device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow, double nug, GroupOut &o) {
+__device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow, double nug, GroupOut &o,
+                                   int w = 0, int nw = 1) {
   bool ok = true;
   double v0 = 0.0, v1 = 0.0, q0 = 0.0, q1 = 0.0;
   const int dummy = tri(nrow) + lane;
@@ -1536,7 +1543,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
     }
     // right-hand-side rows i > k
 #pragma unroll 1
-    for (int i = k + 1 + lane; i < nrow; i += WAVE) {
+    for (int i = k + 1 + lane + w * WAVE; i < nrow; i += nw * WAVE) {
       const double g = mat[tri(i) + k] * ik;
 #pragma unroll
       for (int q = 0; q < NR; ++q) rhs[i * NR + q] = fma(-g, rk[q], rhs[i * NR + q]);
@@ -1548,6 +1555,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
     const int m0 = k + 1;
     const int nt = (nrow - m0 + 15) >> 4;
     const int tlast = tri(nrow - 1);
+    int item = 0;   // tile groups of this step, dealt round robin over the waves
 #pragma unroll 1
     for (int J = 0; J < nt; ++J) {
       int jc[2];
@@ -1564,6 +1572,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
       // its stores; rows past the system read row n - 1 and store to the dummy
 #pragma unroll 1
       for (int I0 = J; I0 < nt; I0 += LDS_TB) {
+        if ((item++) % nw != w) continue;
         const int ib = m0 + 16 * I0 + tr;
         const int tb = tri(ib);
         double a[LDS_TB][2], x[LDS_TB][2][2];
@@ -1592,6 +1601,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
             for (int c = 0; c < 2; ++c) mat[wi[u][rr][c]] = fma(-a[u][rr], fj[c], x[u][rr][c]);
       }
     }
+    if (nw > 1) __syncthreads();   // step k complete in every wave before step k + 1 reads it
   }
   compiler_fence();
   o.v0 = v0;
@@ -1726,25 +1736,6 @@ __device__ inline void point_tile(const PlanDev &P, const double *tab, const dou
   const double th = theta[pt], ph = phi[pt];
   const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
   tile_solve<T, SPIN>(P, tab, map, th, ph, n, out, var, B, B.sel, pt, found, lane);
-}
-
-// One point on the whole wave with the LDS elimination (64 < n <= 128).
-template <int SPIN>
-__device__ inline void point_lds(const PlanDev &P, const double *tab, const double *__restrict__ map,
-                                 const double *__restrict__ theta, const double *__restrict__ phi,
-                                 int64_t n, double *__restrict__ out, double *__restrict__ var,
-                                 const WaveBufs &B, int64_t pt, int lane) {
-  constexpr int NR = (SPIN == 0) ? 2 : 3;
-  const double th = theta[pt], ph = phi[pt];
-  const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
-  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
-  GroupOut o;
-  bool ok = true;
-  if (found) {
-    phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
-    ok = lds_phase_b<SPIN, NR>(B.mat, B.rhs, lane, P.n, nug, o);
-  }
-  if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
 }
 
 // ---------------------------------------------------------------- shared stencils (T + Q/U)

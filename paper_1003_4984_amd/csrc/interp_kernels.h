@@ -208,25 +208,48 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
     point_tile<T, SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
 }
 
-// Main pass for 64 < n <= 128 (spin 2 with 32 < K <= 64): one point per wave,
-// LDS elimination.  The packed systems (up to 66 KB per wave) leave no room for
-// an LDS copy of the table, which is read through the caches (layouts with no
-// table bytes).
+// Main pass for 64 < n <= 128 (spin 2 with 32 < K <= 64) with the LDS
+// elimination.  The packed systems (up to 66 KB) leave no room for an LDS copy
+// of the table, which is read through the caches (layouts with no table bytes).
+// Two waves per target: block b holds one system (the
+// layout's first wave area) and two int flags after it.  Wave 0 searches and
+// gathers the records; both waves assemble and eliminate (rows and tile groups
+// dealt between them, a block barrier per step); wave 0 stores the result.
+// Every barrier is reached by both waves: the loops' bounds are block-uniform.
 template <int SPIN>
-__global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_lds(PlanDev P, const double *__restrict__ map,
-                                                    const double *__restrict__ theta,
-                                                    const double *__restrict__ phi, int64_t n,
-                                                    double *__restrict__ out,
-                                                    double *__restrict__ var, Layout L) {
+__global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const double *__restrict__ map,
+                                               const double *__restrict__ theta,
+                                               const double *__restrict__ phi, int64_t n,
+                                               double *__restrict__ out,
+                                               double *__restrict__ var, Layout L) {
+  constexpr int NR = (SPIN == 0) ? 2 : 3;
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
   const double *tab = kernel_table(lds, P, L);
-  const int wpb = blockDim.x / WAVE;
-  const int wave = threadIdx.x / WAVE;
+  const int w = threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
-  const WaveBufs B = wave_bufs(lds, L, wave);
-  for (int64_t pt = xcd_block() * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb)
-    point_lds<SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
+  const WaveBufs B = wave_bufs(lds, L, 0);
+  int *flag = (int *)(lds + L.tab_bytes + L.wave_bytes);   // search result of wave 0
+  const double nug = (P.nug_policy == FLINTS_NUG_ALWAYS) ? P.eps : 0.0;
+  for (int64_t pt = xcd_block(); pt < n; pt += (int64_t)gridDim.x) {
+    const double th = theta[pt], ph = phi[pt];
+    if (w == 0) {
+      const bool f = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
+      if (f) neighbour_records<SPIN, NR>(P, th, ph, lane, B.sel, B.nb, B.rhs, map);
+      if (lane == 0) flag[0] = f ? 1 : 0;
+    }
+    __syncthreads();
+    const bool found = flag[0] != 0;
+    GroupOut o;
+    bool ok = true;
+    if (found) {
+      assemble<SPIN, NR>(P, tab, B.nb, lane, B.mat, B.rhs, w, 2);
+      __syncthreads();
+      ok = lds_phase_b<SPIN, NR>(B.mat, B.rhs, lane, P.n, nug, o, w, 2);
+    }
+    if (w == 0 && lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
+    __syncthreads();   // the next target's search reuses the system's LDS
+  }
 }
 
 // Main pass and fix-up pass for 64 < n <= 16 T (T = 6, 8; spin 2 with K > 32):
@@ -480,6 +503,8 @@ inline int launch_tile_big(const Plan *p, const double *map, const double *theta
 }
 
 // LDS elimination for 64 < n <= 128 (FP64, paper variance).
+// Main pass with two waves per target (k_interp_lds2), fix-up with one wave per
+// target (the LDS engine of k_fixup).
 template <int SPIN>
 inline int launch_lds(const Plan *p, const double *map, const double *theta, const double *phi,
                       int64_t n, double *out, double *var, hipStream_t s) {
@@ -487,8 +512,34 @@ inline int launch_lds(const Plan *p, const double *map, const double *theta, con
   // the packed system plus WAVE doubles that absorb the masked-off stores
   Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 1, 1, NR, tri(p->d.n) + WAVE);
   L.tab_bytes = 0;   // the table is read through the caches; LDS holds the systems
-  return launch_pair(k_interp_lds<SPIN>, k_fixup<LdsEngine<SPIN>, SPIN>, p, L, 1, map, theta, phi, n, out,
-                     var, s);
+  const DevLimits lim = device_limits();
+  const int lds2 = L.wave_bytes + 16;
+  if (lds2 > lim.lds_max) {
+    set_error("plan needs more LDS than the device offers");
+    return FLINTS_ELIMIT;
+  }
+  auto kern = k_interp_lds2<SPIN>;
+  hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds2);
+  int occ = 0;
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 2 * WAVE, lds2);
+  if (occ < 1) occ = 1;
+  const int64_t blocks = std::max<int64_t>(std::min<int64_t>(n, (int64_t)lim.ncu * occ), 1);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(2 * WAVE), lds2, s, p->d, map, theta, phi, n, out,
+                     var, L);
+  auto esc = k_fixup<LdsEngine<SPIN>, SPIN>;
+  int wpb = 0, eocc = 0;
+  if (!pick_wpb(esc, L, lim, wpb, eocc)) return FLINTS_ELIMIT;
+  const int lds = L.tab_bytes + wpb * L.wave_bytes;
+  hipFuncSetAttribute((const void *)esc, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const int64_t eblocks = std::min<int64_t>(((n + WAVE - 1) / WAVE + wpb - 1) / wpb, (int64_t)lim.ncu * 4);
+  hipLaunchKernelGGL(esc, dim3((unsigned)std::max<int64_t>(eblocks, 1)), dim3(wpb * WAVE), lds, s, p->d, map,
+                     theta, phi, n, out, var, L);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("interpolation kernel launch failed: ") + hipGetErrorString(e));
+    return FLINTS_EDEVICE;
+  }
+  return FLINTS_OK;
 }
 
 template <int SPIN, bool MSE, bool FP32>
