@@ -1499,23 +1499,29 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
 
 // ---------------------------------------------------------------- phase B, 64 < n <= 128
 // Systems above 64 rows (spin 2 with 32 < K <= 64): S + nI = L D L^T (unit lower
-// L, D the pivots) by right-looking elimination in the wave's packed system in
-// LDS.  At step k the trailing triangle a_ij -= a_ik a_jk / d_k (i >= j > k) is
-// cut into 16 x 16 tiles, a 2 x 2 block of entries per lane; column tiles run in
-// the outer loop, so a lane reads its two multipliers a_jk / d_k once per column
-// tile.  Every lane is busy except in the diagonal tiles' upper halves.  The right-hand sides ride
-// along (r_i -= a_ik r_k / d_k), so row k of them is final at step k: with
-// z = L^-1 b, b^T (S + nI)^-1 b = sum_k z_k^2 / d_k, and value and quad
-// accumulate as the row-group and tile engines form them.  Every lane ends with
-// the same sums.  mat holds tri(n) + WAVE doubles: the last WAVE take the stores
-// of masked-off lanes, so the stores need no branch.  Returns false if a pivot
-// is not positive.
+// L, D the pivots) by blocked right-looking elimination of the wave's packed
+// system in LDS, LDS_BS columns per block:
+//   (1) every lane factors the block's pivot rows (LDS_BS x LDS_BS) with their
+//       right-hand sides in registers, accumulating value and quad over the
+//       final r_c r'_c / d_c (z = L^-1 b, b^T (S + nI)^-1 b = sum z_c^2 / d_c);
+//   (2) the panel rows i below the block (one lane each) take the block's
+//       updates in registers, are stored back, and update their right-hand
+//       sides, r_i -= sum_c a_ic r_c / d_c;
+//   (3) the trailing triangle takes the rank-LDS_BS update
+//       a_ij -= sum_c a_ic a_jc / d_c (i >= j past the block) in 16 x 16 tiles,
+//       a 2 x 2 block of entries per lane (tile rows tr, tr + 8 and columns tc,
+//       tc + 8): a lane reads its multipliers a_jc / d_c once per column tile
+//       and the loads of two row tiles are issued before their stores.
+// A block has LDS_BS serial pivots but one pass over the trailing triangle.
+// Every lane ends with the same sums.  mat holds tri(n) + WAVE doubles: the
+// last WAVE take the stores of masked-off lanes, so the stores need no branch.
+// With nw > 1 waves of one block on the system (w = this wave), the panel rows
+// and the tile groups are dealt round robin and block barriers separate the
+// phases; every wave must call it, the assembled system visible to all of
+// them.  Returns false if a pivot is not positive.
 constexpr int LDS_TB = 2;   // row tiles whose loads are issued together
+constexpr int LDS_BS = 4;   // columns eliminated per block
 
-// With nw > 1 waves of one block on the system (w = this wave), the right-hand-
-// side rows and the tile groups of each step are dealt round robin and a block
-// barrier ends every step; every wave must call it, the assembled system
-// visible to all of them.
 template <int SPIN, int NR>
 __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow, double nug, GroupOut &o,
                                    int w = 0, int nw = 1) {
@@ -1524,58 +1530,96 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
   const int dummy = tri(nrow) + lane;
   const int tr = lane >> 3, tc = lane & 7;   // tile rows tr, tr + 8; columns tc, tc + 8
 #pragma unroll 1
-  for (int k = 0; k < nrow; ++k) {
-    compiler_fence();   // step k reads what step k - 1 wrote from other lanes
-    const double dk = mat[tri(k) + k] + nug;
-    ok = ok && (dk > 0.0);
-    const double ik = recip(dk);
-    double rk[NR];
+  for (int K0 = 0; K0 < nrow; K0 += LDS_BS) {
+    compiler_fence();   // block K0 reads what the previous block wrote from other lanes
+    const int nb = min(LDS_BS, nrow - K0);   // columns of this block (the last may be short)
+    // (1) pivot block and its right-hand sides (identity past the system)
+    double Pm[LDS_BS][LDS_BS], Rb[LDS_BS][NR], idv[LDS_BS];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) rk[q] = rhs[k * NR + q];
-    if (SPIN == 0) {
-      v0 = fma(rk[0] * rk[1], ik, v0);
-      q0 = fma(rk[0] * rk[0], ik, q0);
-    } else {
-      v0 = fma(rk[0] * rk[NR - 1], ik, v0);
-      v1 = fma(rk[1] * rk[NR - 1], ik, v1);
-      q0 = fma(rk[0] * rk[0], ik, q0);
-      q1 = fma(rk[1] * rk[1], ik, q1);
+    for (int r = 0; r < LDS_BS; ++r) {
+#pragma unroll
+      for (int c = 0; c <= r; ++c)
+        Pm[r][c] = (r < nb) ? mat[tri(K0 + r) + K0 + c] : (c == r ? 1.0 : 0.0);
+#pragma unroll
+      for (int q = 0; q < NR; ++q) Rb[r][q] = (r < nb) ? rhs[(K0 + r) * NR + q] : 0.0;
     }
-    // right-hand-side rows i > k
+#pragma unroll
+    for (int c = 0; c < LDS_BS; ++c) {
+      const bool live = c < nb;
+      const double dc = Pm[c][c] + (live ? nug : 0.0);
+      ok = ok && (!live || dc > 0.0);
+      idv[c] = recip(dc);
+      if (live) {
+        if (SPIN == 0) {
+          v0 = fma(Rb[c][0] * Rb[c][1], idv[c], v0);
+          q0 = fma(Rb[c][0] * Rb[c][0], idv[c], q0);
+        } else {
+          v0 = fma(Rb[c][0] * Rb[c][NR - 1], idv[c], v0);
+          v1 = fma(Rb[c][1] * Rb[c][NR - 1], idv[c], v1);
+          q0 = fma(Rb[c][0] * Rb[c][0], idv[c], q0);
+          q1 = fma(Rb[c][1] * Rb[c][1], idv[c], q1);
+        }
+      }
+#pragma unroll
+      for (int r = c + 1; r < LDS_BS; ++r) {
+        const double f = Pm[r][c] * idv[c];
+#pragma unroll
+        for (int c2 = c + 1; c2 <= r; ++c2) Pm[r][c2] = fma(-f, Pm[c2][c], Pm[r][c2]);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) Rb[r][q] = fma(-f, Rb[c][q], Rb[r][q]);
+      }
+    }
+    const int m0 = K0 + LDS_BS;   // first row and column past the block
+    if (m0 >= nrow) break;        // block-uniform: the last block has no panel
+    // (2) panel rows i >= m0: the block's columns of row i, then its right-hand sides
 #pragma unroll 1
-    for (int i = k + 1 + lane + w * WAVE; i < nrow; i += nw * WAVE) {
-      const double g = mat[tri(i) + k] * ik;
+    for (int i = m0 + lane + w * WAVE; i < nrow; i += nw * WAVE) {
+      const int ti = tri(i) + K0;
+      double x[LDS_BS];
 #pragma unroll
-      for (int q = 0; q < NR; ++q) rhs[i * NR + q] = fma(-g, rk[q], rhs[i * NR + q]);
+      for (int c = 0; c < LDS_BS; ++c) x[c] = mat[ti + c];
+#pragma unroll
+      for (int c = 0; c < LDS_BS; ++c) {
+        const double g = x[c] * idv[c];
+#pragma unroll
+        for (int c2 = c + 1; c2 < LDS_BS; ++c2) x[c2] = fma(-g, Pm[c2][c], x[c2]);
+      }
+#pragma unroll
+      for (int c = 0; c < LDS_BS; ++c) mat[ti + c] = x[c];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        double acc = rhs[i * NR + q];
+#pragma unroll
+        for (int c = 0; c < LDS_BS; ++c) acc = fma(-x[c] * idv[c], Rb[c][q], acc);
+        rhs[i * NR + q] = acc;
+      }
     }
-    // trailing triangle in 16 x 16 tiles, a 2 x 2 block of entries per lane
-    // (tile rows tr, tr + 8 and columns tc, tc + 8).  Column k is not written in
-    // this step; loads of clamped indices stay inside the system: tri(i) + j <
-    // tri(n) for i, j < n.
-    const int m0 = k + 1;
+    if (nw > 1) __syncthreads(); else compiler_fence();   // the panel is visible to every wave
+    // (3) trailing triangle (rows and columns >= m0).  Loads of clamped indices
+    // stay inside the system: tri(i) + j < tri(n) for i, j < n.
     const int nt = (nrow - m0 + 15) >> 4;
     const int tlast = tri(nrow - 1);
-    int item = 0;   // tile groups of this step, dealt round robin over the waves
+    int item = 0;   // tile groups, dealt round robin over the waves
 #pragma unroll 1
     for (int J = 0; J < nt; ++J) {
       int jc[2];
       bool jv[2];
-      double fj[2];
+      double fj[2][LDS_BS];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int j = m0 + 16 * J + tc + 8 * c;
-        jv[c] = j < nrow;
-        jc[c] = jv[c] ? j : nrow - 1;
-        fj[c] = mat[tri(jc[c]) + k] * ik;
+      for (int cc = 0; cc < 2; ++cc) {
+        const int j = m0 + 16 * J + tc + 8 * cc;
+        jv[cc] = j < nrow;
+        jc[cc] = jv[cc] ? j : nrow - 1;
+        const int tj = tri(jc[cc]) + K0;
+#pragma unroll
+        for (int c = 0; c < LDS_BS; ++c) fj[cc][c] = mat[tj + c] * idv[c];
       }
-      // row tiles in groups of LDS_TB: every load of a group is issued before
-      // its stores; rows past the system read row n - 1 and store to the dummy
 #pragma unroll 1
       for (int I0 = J; I0 < nt; I0 += LDS_TB) {
         if ((item++) % nw != w) continue;
         const int ib = m0 + 16 * I0 + tr;
         const int tb = tri(ib);
-        double a[LDS_TB][2], x[LDS_TB][2][2];
+        double x[LDS_TB][2][2];
         int wi[LDS_TB][2][2];
 #pragma unroll
         for (int u = 0; u < LDS_TB; ++u)
@@ -1585,11 +1629,16 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
             const int i = ib + d;
             const bool iv = i < nrow;
             const int ti = iv ? tb + d * ib + d * (d + 1) / 2 : tlast;
-            a[u][rr] = mat[ti + k];
+            double a[LDS_BS];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              x[u][rr][c] = mat[ti + jc[c]];
-              wi[u][rr][c] = (iv && jv[c] && jc[c] <= i) ? ti + jc[c] : dummy;
+            for (int c = 0; c < LDS_BS; ++c) a[c] = mat[ti + K0 + c];
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+              double v = mat[ti + jc[cc]];
+#pragma unroll
+              for (int c = 0; c < LDS_BS; ++c) v = fma(-a[c], fj[cc][c], v);
+              x[u][rr][cc] = v;
+              wi[u][rr][cc] = (iv && jv[cc] && jc[cc] <= i) ? ti + jc[cc] : dummy;
             }
           }
         compiler_fence();
@@ -1598,10 +1647,10 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
 #pragma unroll
           for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) mat[wi[u][rr][c]] = fma(-a[u][rr], fj[c], x[u][rr][c]);
+            for (int cc = 0; cc < 2; ++cc) mat[wi[u][rr][cc]] = x[u][rr][cc];
       }
     }
-    if (nw > 1) __syncthreads();   // step k complete in every wave before step k + 1 reads it
+    if (nw > 1) __syncthreads();   // block K0 complete in every wave before the next reads it
   }
   compiler_fence();
   o.v0 = v0;

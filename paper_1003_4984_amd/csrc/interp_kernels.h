@@ -213,8 +213,8 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
 // of the table, which is read through the caches (layouts with no table bytes).
 // Two waves per target: block b holds one system (the
 // layout's first wave area) and two int flags after it.  Wave 0 searches and
-// gathers the records; both waves assemble and eliminate (rows and tile groups
-// dealt between them, a block barrier per step); wave 0 stores the result.
+// gathers the records; both waves assemble and eliminate (panel rows and tile
+// groups dealt between them, block barriers per block of columns); wave 0 stores.
 // Every barrier is reached by both waves: the loops' bounds are block-uniform.
 template <int SPIN>
 __global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const double *__restrict__ map,
