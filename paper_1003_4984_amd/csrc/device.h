@@ -1519,10 +1519,10 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
 // and the tile groups are dealt round robin and block barriers separate the
 // phases; every wave must call it, the assembled system visible to all of
 // them.  Returns false if a pivot is not positive.
+// LDS_BS is 4 by default; 8 pays above 96 rows (fewer blocks, more registers).
 constexpr int LDS_TB = 2;   // row tiles whose loads are issued together
-constexpr int LDS_BS = 4;   // columns eliminated per block
 
-template <int SPIN, int NR>
+template <int SPIN, int NR, int LDS_BS = 4>
 __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow, double nug, GroupOut &o,
                                    int w = 0, int nw = 1) {
   bool ok = true;

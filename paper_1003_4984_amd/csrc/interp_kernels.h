@@ -216,7 +216,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
 // gathers the records; both waves assemble and eliminate (panel rows and tile
 // groups dealt between them, block barriers per block of columns); wave 0 stores.
 // Every barrier is reached by both waves: the loops' bounds are block-uniform.
-template <int SPIN>
+template <int SPIN, int BS>
 __global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const double *__restrict__ map,
                                                const double *__restrict__ theta,
                                                const double *__restrict__ phi, int64_t n,
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const doubl
     if (found) {
       assemble<SPIN, NR>(P, tab, B.nb, lane, B.mat, B.rhs, w, 2);
       __syncthreads();
-      ok = lds_phase_b<SPIN, NR>(B.mat, B.rhs, lane, P.n, nug, o, w, 2);
+      ok = lds_phase_b<SPIN, NR, BS>(B.mat, B.rhs, lane, P.n, nug, o, w, 2);
     }
     if (w == 0 && lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
     __syncthreads();   // the next target's search reuses the system's LDS
@@ -518,7 +518,8 @@ inline int launch_lds(const Plan *p, const double *map, const double *theta, con
     set_error("plan needs more LDS than the device offers");
     return FLINTS_ELIMIT;
   }
-  auto kern = k_interp_lds2<SPIN>;
+  // 4-column blocks up to 96 rows, 8-column blocks above (measured at 80, 96, 128)
+  auto kern = p->d.n > 96 ? k_interp_lds2<SPIN, 8> : k_interp_lds2<SPIN, 4>;
   hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds2);
   int occ = 0;
   hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 2 * WAVE, lds2);
