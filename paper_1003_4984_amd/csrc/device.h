@@ -23,11 +23,13 @@
 // z = L^-1 data, so
 //   value = y . z = b^T (S+nI)^-1 data   (paper Eq. best_temperature_field / major_eq)
 //   var   = sigma^2 (1 - y . y)          (paper Eq. gaussvar / gaussvar_pol)
-// without a backward solve.  Three engines:
+// without a backward solve.  Four engines:
 //   row group (n <= 32)   one point per 16-lane row group, lower-triangular rows
 //                          in registers, pivot values by DPP row broadcast;
 //   tile (32 < n <= 64)   one point per wave, blocked on 16 x 16 tiles, panels
 //                          eliminated by row groups, trailing update on FP64 MFMA;
+//   LDS (64 < n <= 128)   blocked L D L^T of the packed system in LDS, one or
+//                          two waves per point;
 //   register row          one row per lane with readlane broadcasts (the MSE
 //                          variance, which needs a backward solve, and the FP32 +
 //                          refinement main pass).
@@ -1169,178 +1171,6 @@ __device__ inline bool tile_phase_b(const double *mat, double *rhs, double *scr,
   return ok;
 }
 
-// ---------------------------------------------------------------- phase B, 64 < n <= 16 T (T = 6, 8)
-// The tile engine for systems of up to 128 rows (spin 2 with K up to 64).  A
-// block column has up to T - 1 panel tiles, but besides the diagonal replica the
-// wave has three row groups, so the panels are eliminated in passes of three
-// (pass g takes block rows J + 3g + 1 .. J + 3g + 3): each pass restarts from
-// the original diagonal tile and right-hand sides (kept in d0 / dr0), which
-// every row group eliminates again alongside its panel of that pass.  All
-// tiles of the block column are read before anything is written, so the
-// staged tiles, the finished panels and the pivots may overlay the packed
-// system.  The trailing tiles stay in registers as in tile_step (these kernels
-// run one wave per SIMD, with the MFMA accumulators in the upper register file).
-template <int T, int J>
-constexpr int mp_passes() {
-  return (T - 1 - J) > 0 ? (T - 1 - J + 2) / 3 : 1;
-}
-
-template <int T, int SPIN, int NR, int J>
-__device__ __forceinline__ void tile_step_mp(TileSys<T> &S, double *scr, double *rhs, const double *mat,
-                                             int l, int nrow, double nug, TileAcc &acc, bool &ok) {
-  constexpr int NP = mp_passes<T, J>();
-  const int rho = l >> 4, x = l & 15;
-  double d0[16], p[NP][16], dr0[NR], pr[NP][NR];
-  if constexpr (J == 0) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) d0[j] = packed_entry(mat, x, j, nrow, nug);
-#pragma unroll
-    for (int g = 0; g < NP; ++g) {
-      const int rp = 3 * g + rho;
-      const bool prow = (rho > 0) && (rp < T);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) p[g][j] = prow ? packed_entry(mat, 16 * rp + x, j, nrow, nug) : 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int r = J; r < T; ++r)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) scr[(r - J) * TILE_D + (4 * v + rho) * TSTR + x] = S.c[r][J][v];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) d0[j] = scr[x * TSTR + j];
-#pragma unroll
-    for (int g = 0; g < NP; ++g) {
-      const int rp = J + 3 * g + rho;
-      const bool prow = (rho > 0) && (rp < T);
-      const int slot = prow ? rp - J : 0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) p[g][j] = prow ? scr[slot * TILE_D + x * TSTR + j] : 0.0;
-    }
-  }
-  const int ir = 16 * J + x;
-#pragma unroll
-  for (int q = 0; q < NR; ++q) dr0[q] = (ir < nrow) ? rhs[ir * NR + q] : 0.0;
-#pragma unroll
-  for (int g = 0; g < NP; ++g) {
-    const int rp = J + 3 * g + rho, ip = 16 * rp + x;
-    const bool prow = (rho > 0) && (rp < T);
-#pragma unroll
-    for (int q = 0; q < NR; ++q) pr[g][q] = (prow && ip < nrow) ? rhs[ip * NR + q] : 0.0;
-  }
-  double *piv = scr + (T - 1) * TILE_D;   // pivots a_kk of this block column
-#pragma unroll
-  for (int g = 0; g < NP; ++g) {
-    double d[16], dr[NR];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) d[j] = d0[j];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) dr[q] = dr0[q];
-    double pv = rbcast<0>(d[0]);
-    double iv = recip(pv);
-    cfor<0, 16>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      ok = ok && (pv > 0.0);
-      piv[k] = pv;
-      const double cd = (x > k) ? d[k] * iv : 0.0;
-      const double cp = p[g][k] * iv;
-      double pn = 1.0, ivn = 1.0;
-      if constexpr (k + 1 < 16) {
-        if constexpr (J + 1 < T) dpp_pd1<k>(p[g][k + 1], d[k + 1], -cp, -cd);
-        else dpp_d1<k>(d[k + 1], -cd);
-        pn = dpp_pivot<k + 1>(d[k + 1]);
-        ivn = recip(pn);
-        dpp_columns<k, k + 2, (J + 1 < T)>(d, p[g], -cp, -cd);
-      }
-#pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        if constexpr (J + 1 < T) dpp_pd1<k>(pr[g][q], dr[q], -cp, -cd);
-        else dpp_d1<k>(dr[q], -cd);
-      }
-      p[g][k] = cp;
-      pv = pn;
-      iv = ivn;
-    });
-    if constexpr (J + 1 < T) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) __asm__ volatile("" ::"v"(p[g][j]));
-#pragma unroll
-      for (int q = 0; q < NR; ++q) __asm__ volatile("" ::"v"(pr[g][q]));
-    }
-    if (g == 0 && rho == 0 && ir < nrow) {
-      const double inv = recip(piv[x]);
-      const double r0 = dr[0], r1 = dr[1];
-      if (SPIN == 0) {
-        acc.v0 = fma(r0 * r1, inv, acc.v0);
-        acc.q0 = fma(r0 * r0, inv, acc.q0);
-      } else {
-        const double r2 = dr[NR - 1];
-        acc.v0 = fma(r0 * r2, inv, acc.v0);
-        acc.v1 = fma(r1 * r2, inv, acc.v1);
-        acc.q0 = fma(r0 * r0, inv, acc.q0);
-        acc.q1 = fma(r1 * r1, inv, acc.q1);
-      }
-    }
-  }
-  if constexpr (J + 1 < T) {
-#pragma unroll
-    for (int g = 0; g < NP; ++g) {
-      const int rp = J + 3 * g + rho, ip = 16 * rp + x;
-      const bool prow = (rho > 0) && (rp < T);
-      if (prow && ip < nrow) {
-#pragma unroll
-        for (int q = 0; q < NR; ++q) rhs[ip * NR + q] = pr[g][q];
-      }
-      if (prow) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) scr[(rp - J - 1) * TILE_D + x * TSTR + j] = p[g][j];
-      }
-    }
-    double fr[T][4], dk[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) dk[m] = piv[4 * m + rho];
-#pragma unroll
-    for (int r = J + 1; r < T; ++r)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) fr[r][m] = scr[(r - J - 1) * TILE_D + x * TSTR + 4 * m + rho];
-#pragma unroll
-    for (int r = J + 1; r < T; ++r)
-#pragma unroll
-      for (int s = J + 1; s <= r; ++s)
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          S.c[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fr[r][m], fr[s][m] * dk[m], S.c[r][s], 0, 0, 0);
-    tile_step_mp<T, SPIN, NR, J + 1>(S, scr, rhs, mat, l, nrow, nug, acc, ok);
-  }
-}
-
-template <int T, int SPIN, int NR>
-__device__ inline bool tile_phase_b_mp(const double *mat, double *rhs, double *scr, int lane_in, int nrow,
-                                       double nug, GroupOut &o) {
-  int l = lane_in;
-  __asm__ volatile("" : "+v"(l));
-  TileSys<T> S;
-  tiles_load<T>(S, mat, l, nrow, nug);
-  TileAcc acc{0.0, 0.0, 0.0, 0.0};
-  bool ok = true;
-  tile_step_mp<T, SPIN, NR, 0>(S, scr, rhs, mat, l, nrow, nug, acc, ok);
-  o.v0 = group_sum<WAVE>(acc.v0);
-  o.qd0 = group_sum<WAVE>(acc.q0);
-  o.v1 = o.qd1 = o.w0 = o.w1 = 0.0;
-  if (SPIN != 0) {
-    o.v1 = group_sum<WAVE>(acc.v1);
-    o.qd1 = group_sum<WAVE>(acc.q1);
-  }
-  return ok;
-}
-
-// Phase B of any tile count: the single-pass engine up to 64 rows, the
-// multi-pass one above.
-template <int T, int SPIN, int NR>
-__device__ inline bool tile_phase_any(const double *mat, double *rhs, double *scr, int lane, int nrow,
-                                      double nug, GroupOut &o) {
-  if constexpr (T <= 4) return tile_phase_b<T, SPIN, NR>(mat, rhs, scr, lane, nrow, nug, o);
-  else return tile_phase_b_mp<T, SPIN, NR>(mat, rhs, scr, lane, nrow, nug, o);
-}
 
 // FP64 phase B: factorise S + nI with the right-hand sides carried, then
 // value = y.z and quad = y.y per point (y = L^-1 b, z = L^-1 data); with MSE
@@ -1685,7 +1515,7 @@ struct TileEngine {
                                double nug, GroupOut &o) {
     if (!found) return true;
     if (!first) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
-    return __all(tile_phase_any<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o));
+    return __all(tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o));
   }
 };
 
@@ -1771,7 +1601,7 @@ __device__ inline void tile_solve(const PlanDev &P, const double *tab, const dou
   bool ok = true;
   if (found) {
     phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, sel, B.nb, B.mat, B.rhs);
-    ok = tile_phase_any<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o);
+    ok = tile_phase_b<T, SPIN, NR>(B.mat, B.rhs, B.mat, lane, P.n, nug, o);
   }
   if (lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
 }

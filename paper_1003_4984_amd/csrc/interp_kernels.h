@@ -252,48 +252,6 @@ __global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const doubl
   }
 }
 
-// Main pass and fix-up pass for 64 < n <= 16 T (T = 6, 8; spin 2 with K > 32):
-// one point per wave with the multi-pass tile engine.  The trailing tiles need
-// the whole register file of a SIMD, so a block holds one wave per SIMD; the
-// systems take up to ~75 KB of LDS per wave, so the correlation table is read
-// from global memory (through the caches) instead of being copied to LDS.
-constexpr int BIG_WPB = 4;
-
-template <int T, int SPIN>
-__global__ __launch_bounds__(BIG_WPB * WAVE) void k_interp_tile_big(PlanDev P, const double *__restrict__ map,
-                                                         const double *__restrict__ theta,
-                                                         const double *__restrict__ phi, int64_t n,
-                                                         double *__restrict__ out,
-                                                         double *__restrict__ var, Layout L) {
-  extern __shared__ double lds_dyn[];
-  char *lds = (char *)lds_dyn;
-  const double *tab = P.tab;   // read through the caches: LDS holds the systems
-  const int wpb = blockDim.x / WAVE;
-  const int wave = threadIdx.x / WAVE;
-  const int lane = threadIdx.x % WAVE;
-  const WaveBufs B = wave_bufs(lds, L, wave);
-  for (int64_t pt = xcd_block() * wpb + wave; pt < n; pt += (int64_t)gridDim.x * wpb)
-    point_tile<T, SPIN>(P, tab, map, theta, phi, n, out, var, B, pt, lane);
-}
-
-template <class Eng, int SPIN>
-__global__ __launch_bounds__(BIG_WPB * WAVE) void k_fixup_big(PlanDev P, const double *__restrict__ map,
-                                                   const double *__restrict__ theta,
-                                                   const double *__restrict__ phi, int64_t n,
-                                                   double *__restrict__ out,
-                                                   double *__restrict__ var, Layout L) {
-  extern __shared__ double lds_dyn[];
-  char *lds = (char *)lds_dyn;
-  const double *tab = P.tab;
-  const int wpb = blockDim.x / WAVE;
-  const int wave = threadIdx.x / WAVE;
-  const int lane = threadIdx.x % WAVE;
-  const WaveBufs B = wave_bufs(lds, L, wave);
-  const int64_t nchunks = (n + WAVE - 1) / WAVE;
-  for (int64_t ch = xcd_block() * wpb + wave; ch < nchunks; ch += (int64_t)gridDim.x * wpb)
-    fixup_chunk<Eng, SPIN>(P, tab, map, theta, phi, n, out, var, B, ch * WAVE, lane);
-}
-
 // Main passes of T + Q/U over targets [s0, s1) with shared stencils: the
 // spin-2 pass (tiles, or row groups for 2K <= 32 rows) writes each target's
 // stencil to stn, the spin-0 pass (row groups) reads it.  s0 is a multiple of
@@ -490,18 +448,6 @@ inline int launch_tile(const Plan *p, const double *map, const double *theta, co
                      phi, n, out, var, s);
 }
 
-// Multi-pass tile path for 16 (T - 2) < n <= 16 T, T = 6, 8 (FP64).
-template <int T, int SPIN>
-inline int launch_tile_big(const Plan *p, const double *map, const double *theta, const double *phi,
-                           int64_t n, double *out, double *var, hipStream_t s) {
-  constexpr int NR = (SPIN == 0) ? 2 : 3;
-  constexpr int SCR = (T - 1) * TILE_D + 16;
-  Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 1, 1, NR, SCR);
-  L.tab_bytes = 0;   // the table stays in global memory (up to 128 KB beside ~75 KB of system)
-  return launch_pair(k_interp_tile_big<T, SPIN>, k_fixup_big<TileEngine<T, SPIN>, SPIN>, p, L, 1, map,
-                     theta, phi, n, out, var, s);
-}
-
 // LDS elimination for 64 < n <= 128 (FP64, paper variance).
 // Main pass with two waves per target (k_interp_lds2), fix-up with one wave per
 // target (the LDS engine of k_fixup).
@@ -553,8 +499,7 @@ inline int launch_spin(const Plan *p, const double *map, const double *theta, co
   }
   if (nrow > 64) {
     // the LDS elimination (FP64, paper variance); plan creation refuses the MSE
-    // variance above 64 rows and runs FP32 plans of this size in FP64.  (The
-    // multi-pass tile engine, launch_tile_big, is switched off.)
+    // variance above 64 rows and runs FP32 plans of this size in FP64
     if constexpr (MSE || FP32) {
       set_error("systems of more than 64 rows run in FP64 with the paper variance only");
       return FLINTS_ELIMIT;
