@@ -157,6 +157,33 @@ def test_edge_inputs(gpu_ok):
     assert var is None and np.all(np.isfinite(out.cpu().numpy()))
 
 
+def test_edge_inputs_lds(gpu_ok):
+    """The LDS elimination (spin-2 K 40, 80 rows) on edge inputs: no targets, one
+    target, invalid directions (NaN outputs, counted), the poles and phi wrap,
+    against the oracle."""
+    nside, lmax, K = 16, 40, 40
+    tt, ee, te, bb = spectra.cl_acoustic(lmax)
+    q, u = synth.synth(-synth.draw_alm(seeds.rng(9, 0, 0), ee, lmax), 2, nside)
+    q, u = q.numpy(), u.numpy()
+    p = fl.Plan(nside, lmax, np.concatenate([ee, 0.1 * ee]), K, 2)
+    m = dev(np.concatenate([q, u]))
+    out, var = fl.interpolate(p, m, dev(np.zeros(0)), dev(np.zeros(0)))
+    assert out.numel() == 0
+    th = np.array([np.nan, -0.1, np.pi + 1e-9, 0.0, np.pi, 0.5, 1.0, 2.0])
+    ph = np.array([0.0, 0.0, 0.0, 0.0, 3.0, np.inf, -31.4, 7.0])
+    p.reset_stats()
+    v, var = run_gpu(p, (q, u), th, ph)
+    assert np.all(np.isnan(v[[0, 1, 2, 5]])) and np.all(np.isnan(var[[0, 1, 2, 5]]))
+    assert p.stats()["bad_inputs"] == 4
+    ok = [3, 4, 6, 7]
+    g = gpu_stencil(p, th[ok], ph[ok])
+    vo, varo, _ = _oracle_on_gpu_stencil(nside, (ee, 0.1 * ee), K, 2, (q, u), th[ok], ph[ok], g)
+    compare(v[ok], var[ok], vo, varo, VAL_TOL, VAR_REL, 1e-9 * p.info()["sigma2"])
+    # a single target gives the same result as within a larger launch
+    v1, var1 = run_gpu(p, (q, u), th[6:7], ph[6:7])
+    assert np.array_equal(v1[0], v[6]) and np.array_equal(var1[0], var[6])
+
+
 def test_pixel_centres_and_zero_deflection(gpu_ok):
     nside, lmax, K = 32, 64, 16
     cl = spectra.cl_config1(lmax, sigma_arcmin=60.0)
