@@ -164,6 +164,26 @@ inline Layout make_layout(int ntab, int nf, int K, int n, int ppw, int nsys, int
   return L;
 }
 
+// Layout of the LDS elimination: the right-hand sides and WAVE spare doubles
+// (the stores of masked-off lanes) overlay the neighbour records, which are dead
+// once the pairs and target covariances are formed (the build writes the
+// right-hand sides last); the packed system follows.  No table copy.
+inline Layout make_layout_lds(int K, int n, int NR) {
+  Layout L = make_layout(0, 1, K, n, 1, 1, NR);
+  L.tab_bytes = 0;
+  const int u0 = L.off_nb;
+  L.off_rhs = u0;
+  L.off_rbuf = al16(u0 + n * NR * 8);
+  const int rec_end = al16(u0 + nb_stride(K) * NBF * 8), spare_end = al16(L.off_rbuf + WAVE * 8);
+  const int region = rec_end > spare_end ? rec_end : spare_end;
+  L.matsz = n * (n + 1) / 2;
+  L.off_mat = region;
+  L.off_col = al16(L.off_mat + L.matsz * 8);
+  const int s = al16(L.off_rings + WAVE * (int)sizeof(RingSpan));   // end of the search view
+  L.wave_bytes = s > L.off_col ? s : L.off_col;
+  return L;
+}
+
 // Block index with the grid regrouped by XCD.  The dispatcher hands blocks to
 // the 8 XCDs of an MI355X round robin (block b runs on XCD b mod 8), and each
 // XCD has its own L2; numbering the blocks of one XCD consecutively makes the
@@ -346,7 +366,9 @@ __device__ __forceinline__ double map_value(const PlanDev &P, const double *__re
   return P.map_f32 ? (double)((const float *)map)[i] : map[i];
 }
 
-template <int SPIN, int NR>
+// DATA false: the data column of the right-hand sides is not written (the LDS
+// elimination, whose right-hand sides overlay the records, writes it later).
+template <int SPIN, int NR, bool DATA = true>
 __device__ void neighbour_records(const PlanDev &P, double th, double ph, int lane, const int *sel,
                                   double *nb, double *rhs, const double *__restrict__ map) {
   double zt, st;
@@ -375,11 +397,13 @@ __device__ void neighbour_records(const PlanDev &P, double th, double ph, int la
       f[3] = R.z * cd; f[4] = R.z * sd; f[5] = -R.s;
       f[6] = -sd;      f[7] = cd;
       // data column of the neighbour's rows (no map: the conditioning probe)
-      if (SPIN == 0) {
-        rhs[(a - 1) * NR + NR - 1] = map_value(P, map, p);
-      } else {
-        rhs[2 * (a - 1) * NR + NR - 1] = map_value(P, map, p);
-        rhs[(2 * (a - 1) + 1) * NR + NR - 1] = map_value(P, map, P.npix + p);
+      if constexpr (DATA) {
+        if (SPIN == 0) {
+          rhs[(a - 1) * NR + NR - 1] = map_value(P, map, p);
+        } else {
+          rhs[2 * (a - 1) * NR + NR - 1] = map_value(P, map, p);
+          rhs[(2 * (a - 1) + 1) * NR + NR - 1] = map_value(P, map, P.npix + p);
+        }
       }
     }
 #pragma unroll
@@ -455,6 +479,35 @@ __device__ __forceinline__ bool pair_cov(const PlanDev &P, const double *tab, co
   return in;
 }
 
+// The off-diagonal pairs (a, b), 1 <= b < a <= K, of the packed system: pair
+// q = (a - 1)(a - 2) / 2 + (b - 1) on lane q mod (nw WAVE) of wave w.
+template <int SPIN>
+__device__ inline void assemble_pairs(const PlanDev &P, const double *tab, const double *nb, int ns, int lane,
+                                      double *mat, bool paper, int w, int nw, bool &range_bad) {
+  // (a, b) comes from q in closed form, so the loop has a fixed trip count
+  const int npairs = P.K * (P.K - 1) / 2;
+#pragma unroll 1
+  for (int q = lane + w * WAVE; q < npairs; q += nw * WAVE) {
+    // m = a - 1 from the hardware square root (within an ulp), then made exact
+    const unsigned uq = (unsigned)q;
+    unsigned m = (unsigned)(0.5f * (1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)q)));
+    m -= (m * (m - 1u) / 2u > uq);
+    m += ((m + 1u) * m / 2u <= uq);
+    const int a = (int)m + 1, b = (int)(uq - m * (m - 1u) / 2u) + 1;
+    double c[4];
+    range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, b, paper, c);
+    if (SPIN == 0) {
+      mat[tri(a - 1) + (b - 1)] = c[0];
+    } else {
+      const int ra = 2 * (a - 1), rb = 2 * (b - 1);
+      mat[tri(ra) + rb] = c[0];
+      mat[tri(ra) + rb + 1] = c[1];
+      mat[tri(ra + 1) + rb] = c[2];
+      mat[tri(ra + 1) + rb + 1] = c[3];
+    }
+  }
+}
+
 // Packed lower triangle of S (row-major, unit diagonal before the nugget) and
 // the right-hand sides [b | data] (spin 0) or [b_Q | b_U | data] (spin 2) in
 // LDS.  First pass: one neighbour per lane, its target covariances, data and
@@ -487,31 +540,56 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
       rhs[(ra + 1) * NR + 1] = c[3];    // Cov(U_a, U_0)
     }
   }
-  // off-diagonal pair q = (a - 1)(a - 2) / 2 + (b - 1), 0 <= q < K (K - 1) / 2,
-  // lanes stride by WAVE; (a, b) comes from q in closed form, so the loop has a
-  // fixed trip count
-  const int npairs = K * (K - 1) / 2;
-#pragma unroll 1
-  for (int q = lane + w * WAVE; q < npairs; q += nw * WAVE) {
-    // m = a - 1 from the hardware square root (within an ulp), then made exact
-    const unsigned uq = (unsigned)q;
-    unsigned m = (unsigned)(0.5f * (1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)q)));
-    m -= (m * (m - 1u) / 2u > uq);
-    m += ((m + 1u) * m / 2u <= uq);
-    const int a = (int)m + 1, b = (int)(uq - m * (m - 1u) / 2u) + 1;
-    double c[4];
-    range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, b, paper, c);
+  assemble_pairs<SPIN>(P, tab, nb, ns, lane, mat, paper, w, nw, range_bad);
+  count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
+}
+
+// Assembly for the LDS elimination, whose right-hand sides overlay the
+// neighbour records: the pairs are written and the target covariances of
+// neighbour a = 1 + lane + w WAVE (K <= 64: at most one per lane) computed into
+// registers while the records are read; after a barrier (nw waves) or a fence
+// (one wave) the right-hand sides are written, the data column read from the
+// map again.  The records must be complete (and visible) on entry.
+template <int SPIN, int NR>
+__device__ void lds_assemble(const PlanDev &P, const double *tab, const double *__restrict__ map,
+                             const int *sel, const double *nb, int lane, double *mat, double *rhs, int w,
+                             int nw) {
+  const int K = P.K;
+  const int ns = nb_stride(K);
+  const bool paper = (P.mode == FLINTS_S2_PAPER);
+  bool range_bad = false;
+  const int a = 1 + lane + w * WAVE;
+  const bool has = a <= K;
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  if (has) {
+    range_bad |= !pair_cov<SPIN>(P, tab, nb, ns, a, 0, paper, c);
     if (SPIN == 0) {
-      mat[tri(a - 1) + (b - 1)] = c[0];
+      mat[tri(a - 1) + a - 1] = 1.0;
     } else {
-      const int ra = 2 * (a - 1), rb = 2 * (b - 1);
-      mat[tri(ra) + rb] = c[0];
-      mat[tri(ra) + rb + 1] = c[1];
-      mat[tri(ra + 1) + rb] = c[2];
-      mat[tri(ra + 1) + rb + 1] = c[3];
+      const int ra = 2 * (a - 1);
+      mat[tri(ra) + ra] = 1.0;
+      mat[tri(ra + 1) + ra] = 0.0;
+      mat[tri(ra + 1) + ra + 1] = 1.0;
     }
   }
+  assemble_pairs<SPIN>(P, tab, nb, ns, lane, mat, paper, w, nw, range_bad);
   count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
+  if (nw > 1) __syncthreads(); else compiler_fence();   // the records are no longer read
+  if (has) {
+    const int64_t p = sel[a - 1];
+    if (SPIN == 0) {
+      rhs[(a - 1) * NR + 0] = c[0];
+      rhs[(a - 1) * NR + NR - 1] = map_value(P, map, p);
+    } else {
+      const int ra = 2 * (a - 1);
+      rhs[ra * NR + 0] = c[0];
+      rhs[ra * NR + 1] = c[1];
+      rhs[(ra + 1) * NR + 0] = c[2];
+      rhs[(ra + 1) * NR + 1] = c[3];
+      rhs[ra * NR + NR - 1] = map_value(P, map, p);
+      rhs[(ra + 1) * NR + NR - 1] = map_value(P, map, P.npix + p);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- phase B
@@ -1343,8 +1421,9 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
 //       tc + 8): a lane reads its multipliers a_jc / d_c once per column tile
 //       and the loads of two row tiles are issued before their stores.
 // A block has LDS_BS serial pivots but one pass over the trailing triangle.
-// Every lane ends with the same sums.  mat holds tri(n) + WAVE doubles: the
-// last WAVE take the stores of masked-off lanes, so the stores need no branch.
+// Every lane ends with the same sums.  Stores of masked-off lanes go to the
+// lane's spare slot dum[lane] (WAVE doubles outside the system), so the stores
+// need no branch.
 // With nw > 1 waves of one block on the system (w = this wave), the panel rows
 // and the tile groups are dealt round robin and block barriers separate the
 // phases; every wave must call it, the assembled system visible to all of
@@ -1353,11 +1432,11 @@ __device__ inline void store_point(const PlanDev &P, int64_t pt, int64_t n, bool
 constexpr int LDS_TB = 2;   // row tiles whose loads are issued together
 
 template <int SPIN, int NR, int LDS_BS = 4>
-__device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow, double nug, GroupOut &o,
-                                   int w = 0, int nw = 1) {
+__device__ inline bool lds_phase_b(double *mat, double *rhs, double *dum, int lane, int nrow, double nug,
+                                   GroupOut &o, int w = 0, int nw = 1) {
   bool ok = true;
   double v0 = 0.0, v1 = 0.0, q0 = 0.0, q1 = 0.0;
-  const int dummy = tri(nrow) + lane;
+  double *const spare = dum + lane;
   const int tr = lane >> 3, tc = lane & 7;   // tile rows tr, tr + 8; columns tc, tc + 8
 #pragma unroll 1
   for (int K0 = 0; K0 < nrow; K0 += LDS_BS) {
@@ -1468,7 +1547,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
 #pragma unroll
               for (int c = 0; c < LDS_BS; ++c) v = fma(-a[c], fj[cc][c], v);
               x[u][rr][cc] = v;
-              wi[u][rr][cc] = (iv && jv[cc] && jc[cc] <= i) ? ti + jc[cc] : dummy;
+              wi[u][rr][cc] = (iv && jv[cc] && jc[cc] <= i) ? ti + jc[cc] : -1;
             }
           }
         compiler_fence();
@@ -1477,7 +1556,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
 #pragma unroll
           for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc) mat[wi[u][rr][cc]] = x[u][rr][cc];
+            for (int cc = 0; cc < 2; ++cc) *(wi[u][rr][cc] >= 0 ? mat + wi[u][rr][cc] : spare) = x[u][rr][cc];
       }
     }
     if (nw > 1) __syncthreads();   // block K0 complete in every wave before the next reads it
@@ -1498,6 +1577,10 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, int lane, int nrow,
 template <int NT, int SPIN>
 struct RowGroupEngine {
   static constexpr int NR = (SPIN == 0) ? 2 : 3;
+  __device__ static void build(const PlanDev &P, const double *tab, const double *map, double th, double ph,
+                               int lane, const WaveBufs &B) {
+    phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
+  }
   __device__ static bool solve(const PlanDev &P, const double *, const double *, double, double, int lane,
                                const WaveBufs &B, bool found, bool, double nug, GroupOut &o) {
     RowSys<NT, NR> S;
@@ -1510,6 +1593,10 @@ struct RowGroupEngine {
 template <int T, int SPIN>
 struct TileEngine {
   static constexpr int NR = (SPIN == 0) ? 2 : 3;
+  __device__ static void build(const PlanDev &P, const double *tab, const double *map, double th, double ph,
+                               int lane, const WaveBufs &B) {
+    phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
+  }
   __device__ static bool solve(const PlanDev &P, const double *tab, const double *map, double th,
                                double ph, int lane, const WaveBufs &B, bool found, bool first,
                                double nug, GroupOut &o) {
@@ -1522,12 +1609,20 @@ struct TileEngine {
 template <int SPIN>
 struct LdsEngine {
   static constexpr int NR = (SPIN == 0) ? 2 : 3;
+  // records without the data column, then the assembly that writes the
+  // right-hand sides (which overlay the records) last
+  __device__ static void build(const PlanDev &P, const double *tab, const double *map, double th, double ph,
+                               int lane, const WaveBufs &B) {
+    neighbour_records<SPIN, NR, false>(P, th, ph, lane, B.sel, B.nb, B.rhs, map);
+    compiler_fence();
+    lds_assemble<SPIN, NR>(P, tab, map, B.sel, B.nb, lane, B.mat, B.rhs, 0, 1);
+  }
   __device__ static bool solve(const PlanDev &P, const double *tab, const double *map, double th,
                                double ph, int lane, const WaveBufs &B, bool found, bool first,
                                double nug, GroupOut &o) {
     if (!found) return true;
-    if (!first) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
-    return lds_phase_b<SPIN, NR>(B.mat, B.rhs, lane, P.n, nug, o);
+    if (!first) build(P, tab, map, th, ph, lane, B);
+    return lds_phase_b<SPIN, NR>(B.mat, B.rhs, B.rbuf, lane, P.n, nug, o);
   }
 };
 
@@ -1730,7 +1825,7 @@ __device__ inline void fixup_chunk(const PlanDev &P, const double *tab, const do
     const int64_t pt = p0 + bit;
     const double th = theta[pt], ph = phi[pt];
     const bool found = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
-    if (found) phase_a_build<SPIN, NR>(P, tab, map, th, ph, lane, B.sel, B.nb, B.mat, B.rhs);
+    if (found) Eng::build(P, tab, map, th, ph, lane, B);
     GroupOut o;
     double nug = nug0;
     bool ok = false, first = true;

@@ -211,13 +211,13 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
 // Main pass for 64 < n <= 128 (spin 2 with 32 < K <= 64) with the LDS
 // elimination.  The packed systems (up to 66 KB) leave no room for an LDS copy
 // of the table, which is read through the caches (layouts with no table bytes).
-// Two waves per target: block b holds one system (the
+// NW waves per target (2 or 4): block b holds one system (the
 // layout's first wave area) and two int flags after it.  Wave 0 searches and
-// gathers the records; both waves assemble and eliminate (panel rows and tile
+// gathers the records; all waves assemble and eliminate (panel rows and tile
 // groups dealt between them, block barriers per block of columns); wave 0 stores.
-// Every barrier is reached by both waves: the loops' bounds are block-uniform.
-template <int SPIN, int BS>
-__global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const double *__restrict__ map,
+// Every barrier is reached by every wave: the loops' bounds are block-uniform.
+template <int SPIN, int BS, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_interp_lds2(PlanDev P, const double *__restrict__ map,
                                                const double *__restrict__ theta,
                                                const double *__restrict__ phi, int64_t n,
                                                double *__restrict__ out,
@@ -235,7 +235,8 @@ __global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const doubl
     const double th = theta[pt], ph = phi[pt];
     if (w == 0) {
       const bool f = phase_a_search(P, th, ph, lane, B.cu, B.ci, B.rs, B.sel);
-      if (f) neighbour_records<SPIN, NR>(P, th, ph, lane, B.sel, B.nb, B.rhs, map);
+      // records without the data column: the right-hand sides overlay them
+      if (f) neighbour_records<SPIN, NR, false>(P, th, ph, lane, B.sel, B.nb, B.rhs, map);
       if (lane == 0) flag[0] = f ? 1 : 0;
     }
     __syncthreads();
@@ -243,9 +244,9 @@ __global__ __launch_bounds__(2 * WAVE) void k_interp_lds2(PlanDev P, const doubl
     GroupOut o;
     bool ok = true;
     if (found) {
-      assemble<SPIN, NR>(P, tab, B.nb, lane, B.mat, B.rhs, w, 2);
+      lds_assemble<SPIN, NR>(P, tab, map, B.sel, B.nb, lane, B.mat, B.rhs, w, NW);
       __syncthreads();
-      ok = lds_phase_b<SPIN, NR, BS>(B.mat, B.rhs, lane, P.n, nug, o, w, 2);
+      ok = lds_phase_b<SPIN, NR, BS>(B.mat, B.rhs, B.rbuf, lane, P.n, nug, o, w, NW);
     }
     if (w == 0 && lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
     __syncthreads();   // the next target's search reuses the system's LDS
@@ -455,23 +456,28 @@ template <int SPIN>
 inline int launch_lds(const Plan *p, const double *map, const double *theta, const double *phi,
                       int64_t n, double *out, double *var, hipStream_t s) {
   constexpr int NR = (SPIN == 0) ? 2 : 3;
-  // the packed system plus WAVE doubles that absorb the masked-off stores
-  Layout L = make_layout(p->d.ntab, p->d.nfun, p->d.K, p->d.n, 1, 1, NR, tri(p->d.n) + WAVE);
-  L.tab_bytes = 0;   // the table is read through the caches; LDS holds the systems
+  // right-hand sides and spare slots over the records, then the packed system;
+  // the table is read through the caches
+  const Layout L = make_layout_lds(p->d.K, p->d.n, NR);
   const DevLimits lim = device_limits();
   const int lds2 = L.wave_bytes + 16;
   if (lds2 > lim.lds_max) {
     set_error("plan needs more LDS than the device offers");
     return FLINTS_ELIMIT;
   }
-  // 4-column blocks up to 96 rows, 8-column blocks above (measured at 80, 96, 128)
-  auto kern = p->d.n > 96 ? k_interp_lds2<SPIN, 8> : k_interp_lds2<SPIN, 4>;
+  // 4-column blocks up to 96 rows, 8-column blocks above (measured at 80, 96,
+  // 128 rows); four waves per target where LDS holds at most two systems per CU,
+  // so that every SIMD runs two waves, two waves per target otherwise
+  const bool four = lim.lds_max / lds2 <= 2;
+  auto kern = p->d.n <= 96 ? k_interp_lds2<SPIN, 4, 2>
+                           : (four ? k_interp_lds2<SPIN, 8, 4> : k_interp_lds2<SPIN, 8, 2>);
+  const int nw = (p->d.n > 96 && four) ? 4 : 2;
   hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds2);
   int occ = 0;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 2 * WAVE, lds2);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, nw * WAVE, lds2);
   if (occ < 1) occ = 1;
   const int64_t blocks = std::max<int64_t>(std::min<int64_t>(n, (int64_t)lim.ncu * occ), 1);
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(2 * WAVE), lds2, s, p->d, map, theta, phi, n, out,
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(nw * WAVE), lds2, s, p->d, map, theta, phi, n, out,
                      var, L);
   auto esc = k_fixup<LdsEngine<SPIN>, SPIN>;
   int wpb = 0, eocc = 0;
