@@ -642,6 +642,16 @@ def leg_serving(fl, torch, inp_main, rate=1.0, n_req=16):
     return rep
 
 
+def _all_parity_ok(d):
+    """False if any parity sample nested in the legs' results broke its tolerance
+    or a leg failed; the headline's own gate stays parity_ok."""
+    if isinstance(d, dict):
+        if "error" in d or d.get("parity_ok") is False:
+            return False
+        return all(_all_parity_ok(v) for v in d.values())
+    return True
+
+
 def run_legs(fl, torch, inp_main, pool, nw):
     legs = {}
     for name, fn in (("nside512_fp64_vs_fp32ir", lambda: leg_nside512(fl, torch, pool, nw)),
@@ -807,6 +817,7 @@ def main():
     if not args.no_legs and args.workload == "nside4096":
         out_t = var_t = out_qu = var_qu = None      # the legs need the memory
         result["legs"] = run_legs(fl, torch, inp, pool, nw)
+        result["legs_parity_ok"] = _all_parity_ok(result["legs"])
     if pool is not None:
         pool.close()
         pool.join()
