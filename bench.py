@@ -652,7 +652,7 @@ def _all_parity_ok(d):
     return True
 
 
-def run_legs(fl, torch, inp_main, pool, nw):
+def run_legs(fl, torch, inp_main, pool, nw, only=None):
     legs = {}
     for name, fn in (("nside512_fp64_vs_fp32ir", lambda: leg_nside512(fl, torch, pool, nw)),
                      ("supersample_2048_to_4096", lambda: leg_supersample(fl, torch)),
@@ -660,6 +660,8 @@ def run_legs(fl, torch, inp_main, pool, nw):
                      ("large_systems_K48", lambda: leg_large_systems(fl, torch, inp_main, pool)),
                      ("lensing_pipeline", lambda: leg_lensing_pipeline(fl, torch, inp_main, pool)),
                      ("serving_cfg5", lambda: leg_serving(fl, torch, inp_main))):
+        if only is not None and name not in only:
+            continue
         log(f"leg {name}")
         try:
             legs[name] = fn()
@@ -684,6 +686,8 @@ def main():
                          "call per plan (separate)")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the extra measurements (N_side 512 FP64 and FP32+IR, supersampling, serving)")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated names of the extra measurements to run (default: all)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy of "
                          "known size that calibrates HBM traffic counters)")
@@ -816,7 +820,8 @@ def main():
         result["parity_ok"] = parity["parity_ok"]
     if not args.no_legs and args.workload == "nside4096":
         out_t = var_t = out_qu = var_qu = None      # the legs need the memory
-        result["legs"] = run_legs(fl, torch, inp, pool, nw)
+        only = None if args.legs is None else set(args.legs.split(","))
+        result["legs"] = run_legs(fl, torch, inp, pool, nw, only)
         result["legs_parity_ok"] = _all_parity_ok(result["legs"])
     if pool is not None:
         pool.close()
