@@ -480,10 +480,12 @@ __device__ __forceinline__ bool pair_cov(const PlanDev &P, const double *tab, co
 }
 
 // The off-diagonal pairs (a, b), 1 <= b < a <= K, of the packed system: pair
-// q = (a - 1)(a - 2) / 2 + (b - 1) on lane q mod (nw WAVE) of wave w.
+// q = (a - 1)(a - 2) / 2 + (b - 1) on lane q mod (nw WAVE) of wave w.  Returns
+// true if a pair distance lay beyond the table.
 template <int SPIN>
-__device__ inline void assemble_pairs(const PlanDev &P, const double *tab, const double *nb, int ns, int lane,
-                                      double *mat, bool paper, int w, int nw, bool &range_bad) {
+__device__ __forceinline__ bool assemble_pairs(const PlanDev &P, const double *tab, const double *nb, int ns,
+                                               int lane, double *mat, bool paper, int w, int nw) {
+  bool range_bad = false;
   // (a, b) comes from q in closed form, so the loop has a fixed trip count
   const int npairs = P.K * (P.K - 1) / 2;
 #pragma unroll 1
@@ -506,6 +508,7 @@ __device__ inline void assemble_pairs(const PlanDev &P, const double *tab, const
       mat[tri(ra + 1) + rb + 1] = c[3];
     }
   }
+  return range_bad;
 }
 
 // Packed lower triangle of S (row-major, unit diagonal before the nugget) and
@@ -540,7 +543,7 @@ __device__ void assemble(const PlanDev &P, const double *tab, const double *nb, 
       rhs[(ra + 1) * NR + 1] = c[3];    // Cov(U_a, U_0)
     }
   }
-  assemble_pairs<SPIN>(P, tab, nb, ns, lane, mat, paper, w, nw, range_bad);
+  range_bad |= assemble_pairs<SPIN>(P, tab, nb, ns, lane, mat, paper, w, nw);
   count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
 }
 
@@ -572,7 +575,7 @@ __device__ void lds_assemble(const PlanDev &P, const double *tab, const double *
       mat[tri(ra + 1) + ra + 1] = 1.0;
     }
   }
-  assemble_pairs<SPIN>(P, tab, nb, ns, lane, mat, paper, w, nw, range_bad);
+  range_bad |= assemble_pairs<SPIN>(P, tab, nb, ns, lane, mat, paper, w, nw);
   count_event(P.counters + CNT_TABLE_RANGE, range_bad, lane);
   if (nw > 1) __syncthreads(); else compiler_fence();   // the records are no longer read
   if (has) {
