@@ -1532,7 +1532,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, double *dum, int la
         const int ib = m0 + 16 * I0 + tr;
         const int tb = tri(ib);
         double x[LDS_TB][2][2];
-        int wi[LDS_TB][2][2];
+        double *pst[LDS_TB][2][2];   // where each entry is stored (its slot or the spare)
 #pragma unroll
         for (int u = 0; u < LDS_TB; ++u)
 #pragma unroll
@@ -1546,11 +1546,12 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, double *dum, int la
             for (int c = 0; c < LDS_BS; ++c) a[c] = mat[ti + K0 + c];
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
-              double v = mat[ti + jc[cc]];
+              double *const pe = mat + ti + jc[cc];
+              double v = *pe;
 #pragma unroll
               for (int c = 0; c < LDS_BS; ++c) v = fma(-a[c], fj[cc][c], v);
               x[u][rr][cc] = v;
-              wi[u][rr][cc] = (iv && jv[cc] && jc[cc] <= i) ? ti + jc[cc] : -1;
+              pst[u][rr][cc] = (iv && jv[cc] && jc[cc] <= i) ? pe : spare;
             }
           }
         compiler_fence();
@@ -1559,7 +1560,7 @@ __device__ inline bool lds_phase_b(double *mat, double *rhs, double *dum, int la
 #pragma unroll
           for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc) *(wi[u][rr][cc] >= 0 ? mat + wi[u][rr][cc] : spare) = x[u][rr][cc];
+            for (int cc = 0; cc < 2; ++cc) *pst[u][rr][cc] = x[u][rr][cc];
       }
     }
     if (nw > 1) __syncthreads();   // block K0 complete in every wave before the next reads it

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_interp_lds2(PlanDev P, const doub
   extern __shared__ double lds_dyn[];
   char *lds = (char *)lds_dyn;
   const double *tab = kernel_table(lds, P, L);
-  const int w = threadIdx.x / WAVE;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wave-uniform
   const int lane = threadIdx.x % WAVE;
   const WaveBufs B = wave_bufs(lds, L, 0);
   int *flag = (int *)(lds + L.tab_bytes + L.wave_bytes);   // search result of wave 0
