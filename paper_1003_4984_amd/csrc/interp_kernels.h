@@ -216,7 +216,7 @@ __global__ __launch_bounds__(MAX_WPB * WAVE) void k_interp_tile(PlanDev P, const
 // gathers the records; all waves assemble and eliminate (panel rows and tile
 // groups dealt between them, block barriers per block of columns); wave 0 stores.
 // Every barrier is reached by every wave: the loops' bounds are block-uniform.
-template <int SPIN, int BS, int NW>
+template <int SPIN, int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_interp_lds2(PlanDev P, const double *__restrict__ map,
                                                const double *__restrict__ theta,
                                                const double *__restrict__ phi, int64_t n,
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_interp_lds2(PlanDev P, const doub
     if (found) {
       lds_assemble<SPIN, NR>(P, tab, map, B.sel, B.nb, lane, B.mat, B.rhs, w, NW);
       __syncthreads();
-      ok = lds_phase_b<SPIN, NR, BS>(B.mat, B.rhs, B.rbuf, lane, P.n, nug, o, w, NW);
+      ok = lds_phase_b<SPIN, NR>(B.mat, B.rhs, B.rbuf, lane, P.n, nug, o, w, NW);
     }
     if (w == 0 && lane == 0) store_point<SPIN>(P, pt, n, found, ok, FAIL64_BITS, o, nug, false, out, var);
     __syncthreads();   // the next target's search reuses the system's LDS
@@ -450,8 +450,8 @@ inline int launch_tile(const Plan *p, const double *map, const double *theta, co
 }
 
 // LDS elimination for 64 < n <= 128 (FP64, paper variance).
-// Main pass with two waves per target (k_interp_lds2), fix-up with one wave per
-// target (the LDS engine of k_fixup).
+// Main pass with two or four waves per target (k_interp_lds2), fix-up with one
+// wave per target (the LDS engine of k_fixup, the same elimination).
 template <int SPIN>
 inline int launch_lds(const Plan *p, const double *map, const double *theta, const double *phi,
                       int64_t n, double *out, double *var, hipStream_t s) {
@@ -465,16 +465,25 @@ inline int launch_lds(const Plan *p, const double *map, const double *theta, con
     set_error("plan needs more LDS than the device offers");
     return FLINTS_ELIMIT;
   }
-  // 4-column blocks up to 96 rows, 8-column blocks above (measured at 80, 96,
-  // 128 rows); four waves per target where LDS holds at most two systems per CU,
-  // so that every SIMD runs two waves, two waves per target otherwise
-  const bool four = lim.lds_max / lds2 <= 2;
-  auto kern = p->d.n <= 96 ? k_interp_lds2<SPIN, 4, 2>
-                           : (four ? k_interp_lds2<SPIN, 8, 4> : k_interp_lds2<SPIN, 8, 2>);
-  const int nw = (p->d.n > 96 && four) ? 4 : 2;
+  // Two waves per target, or four where a CU holds at most two systems, so
+  // that every SIMD runs two waves.  Systems per CU: the occupancy API's count,
+  // bounded by the LDS rounded up to 512-byte granules (at 112 rows, 54,576 B,
+  // the API counts three two-wave blocks but the measured rate is that of two;
+  // four waves run 25 % faster there, and 24 % slower at 104 rows, where three fit).
+  constexpr int LDS_GRANULE = 512;
+  const int fit = lim.lds_max / ((lds2 + LDS_GRANULE - 1) / LDS_GRANULE * LDS_GRANULE);
+  auto kern = k_interp_lds2<SPIN, 2>;
+  int nw = 2, occ = 0;
   hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds2);
-  int occ = 0;
   hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, nw * WAVE, lds2);
+  occ = std::min(occ, fit);
+  if (occ <= 2) {
+    kern = k_interp_lds2<SPIN, 4>;
+    nw = 4;
+    hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds2);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, nw * WAVE, lds2);
+    occ = std::min(occ, fit);
+  }
   if (occ < 1) occ = 1;
   const int64_t blocks = std::max<int64_t>(std::min<int64_t>(n, (int64_t)lim.ncu * occ), 1);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(nw * WAVE), lds2, s, p->d, map, theta, phi, n, out,
