@@ -28,8 +28,8 @@
 //                          in registers, pivot values by DPP row broadcast;
 //   tile (32 < n <= 64)   one point per wave, blocked on 16 x 16 tiles, panels
 //                          eliminated by row groups, trailing update on FP64 MFMA;
-//   LDS (64 < n <= 128)   blocked L D L^T of the packed system in LDS, one or
-//                          two waves per point;
+//   LDS (64 < n <= 128)   blocked L D L^T of the packed system in LDS, two or
+//                          four waves per point (one in the fix-up);
 //   register row          one row per lane with readlane broadcasts (the MSE
 //                          variance, which needs a backward solve, and the FP32 +
 //                          refinement main pass).

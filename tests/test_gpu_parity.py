@@ -100,8 +100,8 @@ def test_parity_cfg1(cfg1):
 @pytest.mark.parametrize("K", [8, 16, 24, 32, 33, 40, 48, 57, 64])
 def test_parity_spin2(gpu_ok, mode, K):
     """K <= 32: row groups and the 64-row tile engine; K = 33 .. 64 (66 to 128
-    rows): the LDS elimination, in blocks of 4 columns up to 96 rows and 8 above
-    (K 33 and 57 end in a short block)."""
+    rows): the LDS elimination in blocks of 8 columns, two waves per system up to
+    K 55 and four from K 56 (K 33 and 57 end in a short block)."""
     nside, lmax = 64, 160
     tt, ee, te, bb = spectra.cl_acoustic(lmax)
     bb = 0.1 * ee
