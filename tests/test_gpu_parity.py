@@ -20,6 +20,15 @@ pytestmark = pytest.mark.gpu
 
 VAL_TOL = 1e-8
 VAR_REL = 1e-4
+# Systems above 64 rows (spin 2, K > 32).  The covariance entries come from the
+# tabulated correlation function (paper App. B), pinned to 1e-11 against the
+# exact sums, and the nugget of Sec. 2.4 leaves these systems far worse
+# conditioned (condition numbers up to 7e8 at K 64, against 3e6 at K 32).  On
+# the inputs of test_parity_spin2 the oracle's values move by up to 2.9e-8 (K 48),
+# 1.0e-7 (K 56) and 1.3e-7 (K 64) of their rms under random relative entry errors
+# of 1e-11, against 7.9e-9 at K 32; two FP64 solvers (Cholesky, LU) on the same
+# entries agree to 3e-12.
+VAL_TOL_LARGE = 2e-7
 
 
 @pytest.fixture(scope="module")
@@ -97,11 +106,12 @@ def test_parity_cfg1(cfg1):
 
 
 @pytest.mark.parametrize("mode", [fl.S2_FULL, fl.S2_PAPER])
-@pytest.mark.parametrize("K", [8, 16, 24, 32, 33, 40, 48, 57, 64])
+@pytest.mark.parametrize("K", [8, 16, 24, 32, 33, 40, 48, 52, 56, 57, 64])
 def test_parity_spin2(gpu_ok, mode, K):
     """K <= 32: row groups and the 64-row tile engine; K = 33 .. 64 (66 to 128
     rows): the LDS elimination in blocks of 8 columns, two waves per system up to
-    K 55 and four from K 56 (K 33 and 57 end in a short block)."""
+    K 55 (K 52: three systems per CU) and four from K 56 (K 56: the LDS rounded to
+    512-byte granules leaves room for two); K 33 and 57 end in a short block."""
     nside, lmax = 64, 160
     tt, ee, te, bb = spectra.cl_acoustic(lmax)
     bb = 0.1 * ee
@@ -116,7 +126,7 @@ def test_parity_spin2(gpu_ok, mode, K):
     vo, varo, _ = _oracle_on_gpu_stencil(nside, (ee, bb), K, 2, (q, u), th, ph, g,
                                          mode="paper" if mode == fl.S2_PAPER else "full")
     s2 = p.info()["sigma2"]
-    compare(v, var, vo, varo, VAL_TOL, VAR_REL, 1e-9 * s2)
+    compare(v, var, vo, varo, VAL_TOL if K <= 32 else VAL_TOL_LARGE, VAR_REL, 1e-9 * s2)
 
 
 @pytest.mark.parametrize("K", [1, 7, 16, 24, 33, 48, 64])
