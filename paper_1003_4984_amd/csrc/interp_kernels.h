@@ -451,7 +451,8 @@ inline int launch_tile(const Plan *p, const double *map, const double *theta, co
 
 // LDS elimination for 64 < n <= 128 (FP64, paper variance).
 // Main pass with two or four waves per target (k_interp_lds2), fix-up with one
-// wave per target (the LDS engine of k_fixup, the same elimination).
+// wave per target (the LDS engine of k_fixup: the same elimination in 4-column
+// blocks).
 template <int SPIN>
 inline int launch_lds(const Plan *p, const double *map, const double *theta, const double *phi,
                       int64_t n, double *out, double *var, hipStream_t s) {
